@@ -1,0 +1,152 @@
+"""FP64 CPU oracle for the sttsm operation C := [A; X, ..., X].
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the GPU library (``paper_1301_7744_amd``) and never imports it.
+
+Paper: Schatz, Low, van de Geijn, Kolda, "Exploiting Symmetry in Tensors for
+High Performance: Multiplication with Symmetric Tensors" (arXiv:1301.7744).
+
+Dense tensors here are NumPy arrays in Fortran order, indexed naturally as
+``T[i_0, ..., i_{m-1}]``; their memory order is then the paper's dimensional
+order (App. A).  X is a (p, n) array, ``X[j, i] = chi_{j i}``.
+
+Components
+  direct_sum  (O1)  literal sum of §2.5 over all n^m terms, every output entry
+  chain       (O2)  successive dense mode products (§5.2, Figure 1 bottom right)
+  entry       (O3)  one output entry by the literal sum
+  closed_forms (O4) m=2 matrix identity, rank-1 / rank-r forms
+  bcss_ref          independent BCSS enumerator, pack and unpack
+  costs             storage / work counts by enumeration and by the paper's formulas
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so (gcc, -O3, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O3", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
+               "-fPIC", "-shared", "-std=c11", "-o", tmp, _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.oracle_entry.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, dp, i64p, dp]
+        lib.oracle_direct_sum.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, dp, dp]
+        lib.oracle_mode_product.argtypes = [ctypes.c_int, i64p, dp, ctypes.c_int, dp, ctypes.c_int64, dp]
+        lib.oracle_chain.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, dp, dp,
+                                     ctypes.POINTER(dp)]
+        lib.oracle_num_threads.argtypes = []
+        for f in (lib.oracle_entry, lib.oracle_direct_sum, lib.oracle_mode_product,
+                  lib.oracle_chain, lib.oracle_num_threads):
+            f.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _as_dense_f64(T: np.ndarray) -> np.ndarray:
+    return np.asfortranarray(np.asarray(T, dtype=np.float64))
+
+
+def _check(A: np.ndarray, X: np.ndarray):
+    m = A.ndim
+    p, n = X.shape
+    if m < 1 or m > 8 or any(d != n for d in A.shape):
+        raise ValueError("A must be order 1..8 with every extent equal to X.shape[1]")
+    return m, n, p
+
+
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return _load().oracle_num_threads()
+
+
+def entry(A: np.ndarray, X: np.ndarray, j) -> float:
+    """O3: one entry gamma_j by the literal n^m-term sum (§2.5)."""
+    m, n, p = _check(A, X)
+    A64, X64 = _as_dense_f64(A), np.ascontiguousarray(X, dtype=np.float64)
+    jj = np.ascontiguousarray(j, dtype=np.int64)
+    if jj.shape != (m,):
+        raise ValueError("j must have m entries")
+    out = ctypes.c_double(0.0)
+    rc = _load().oracle_entry(m, n, p, _dptr(A64), _dptr(X64),
+                              jj.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(out))
+    if rc:
+        raise ValueError("oracle_entry rejected its arguments")
+    return out.value
+
+
+def direct_sum(A: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """O1: every entry of C by the literal sum of §2.5; cost (m+1) n^m p^m."""
+    m, n, p = _check(A, X)
+    A64, X64 = _as_dense_f64(A), np.ascontiguousarray(X, dtype=np.float64)
+    C = np.zeros((p,) * m, dtype=np.float64, order="F")
+    rc = _load().oracle_direct_sum(m, n, p, _dptr(A64), _dptr(X64), _dptr(C))
+    if rc:
+        raise ValueError("oracle_direct_sum rejected its arguments")
+    return C
+
+
+def mode_product(T: np.ndarray, k: int, B: np.ndarray) -> np.ndarray:
+    """out = T x_k B (App. A): B is (J, T.shape[k]); out has extent J in mode k."""
+    T64 = _as_dense_f64(T)
+    B64 = np.ascontiguousarray(B, dtype=np.float64)
+    if B64.ndim != 2 or B64.shape[1] != T64.shape[k]:
+        raise ValueError("B must be (J, T.shape[k])")
+    dims = np.asarray(T64.shape, dtype=np.int64)
+    shape = list(T64.shape)
+    shape[k] = B64.shape[0]
+    out = np.zeros(shape, dtype=np.float64, order="F")
+    rc = _load().oracle_mode_product(T64.ndim, dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                     _dptr(T64), k, _dptr(B64), B64.shape[0], _dptr(out))
+    if rc:
+        raise ValueError("oracle_mode_product rejected its arguments")
+    return out
+
+
+def chain(A: np.ndarray, X: np.ndarray, keep_temps: bool = False):
+    """O2: C by successive dense mode products, mode m-1 first (§5.2, Figure 1).
+
+    With keep_temps, also returns {k: T^(k)} for k = 1..m-1, where T^(k) has
+    extent n in modes 0..k-1 and p in modes k..m-1.
+    """
+    m, n, p = _check(A, X)
+    A64, X64 = _as_dense_f64(A), np.ascontiguousarray(X, dtype=np.float64)
+    C = np.zeros((p,) * m, dtype=np.float64, order="F")
+    temps = {}
+    tptrs = None
+    if keep_temps and m > 1:
+        arr_t = ctypes.POINTER(ctypes.c_double) * m
+        tptrs = arr_t()
+        for k in range(1, m):
+            temps[k] = np.zeros((n,) * k + (p,) * (m - k), dtype=np.float64, order="F")
+            tptrs[k] = _dptr(temps[k])
+    rc = _load().oracle_chain(m, n, p, _dptr(A64), _dptr(X64), _dptr(C), tptrs)
+    if rc:
+        raise MemoryError("oracle_chain failed (%d)" % rc)
+    return (C, temps) if keep_temps else C

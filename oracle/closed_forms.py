@@ -1,0 +1,36 @@
+"""Closed forms for sttsm that hold without any algorithm (O4).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def matrix_case(A: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """m = 2: [A; X, X] = X A X^T (§3.1), by a library matrix product in FP64."""
+    A64 = np.asarray(A, dtype=np.float64)
+    X64 = np.asarray(X, dtype=np.float64)
+    return X64 @ A64 @ X64.T
+
+
+def outer_power(v: np.ndarray, m: int) -> np.ndarray:
+    """v o v o ... o v (m factors) as a Fortran-ordered dense tensor."""
+    out = np.asarray(v, dtype=np.float64)
+    for _ in range(m - 1):
+        out = np.multiply.outer(out, v)
+    return np.asfortranarray(out)
+
+
+def rank_r(lams, vecs, X: np.ndarray, m: int) -> np.ndarray:
+    """C for A = sum_i lam_i a_i^{o m}:  sum_i lam_i (X a_i)^{o m}.
+
+    Follows from the multilinearity of the defining sum in §2.5: every mode
+    multiplies the same vector a_i by X.  This is the symmetric CP form the
+    paper names as a use of sttsm (§2.5)."""
+    X64 = np.asarray(X, dtype=np.float64)
+    out = None
+    for lam, a in zip(lams, vecs):
+        term = lam * outer_power(X64 @ np.asarray(a, dtype=np.float64), m)
+        out = term if out is None else out + term
+    return np.asfortranarray(out)
