@@ -1,0 +1,178 @@
+/*
+ * sttsm.h -- C ABI of libsttsm.so: symmetric tensor times same matrix on
+ * MI355X (gfx950), with tensors in Blocked Compact Symmetric Storage.
+ *
+ * Method: Schatz, Low, van de Geijn, Kolda, "Exploiting Symmetry in Tensors
+ * for High Performance: Multiplication with Symmetric Tensors"
+ * (arXiv:1301.7744).
+ *
+ * General rules
+ *  - Every function that returns `int` returns an sttsm_status.  Nothing
+ *    aborts or throws across this boundary; sttsm_last_error() gives a
+ *    message for the calling thread.
+ *  - Arguments are validated on the host before anything is launched.
+ *  - `stream` is a hipStream_t passed as void* (NULL: the null stream).
+ *    Launches are asynchronous on it; a device fault surfaces as
+ *    STTSM_EHIP from a later call or from the caller's own synchronisation.
+ *  - The caller owns every buffer passed in (device memory unless stated).
+ *    The library owns only its plan cache (host and device index tables,
+ *    built once per shape and kept until the process ends) and the serving
+ *    bookkeeping.
+ *  - Dense tensors are in dimensional order (App. A): element
+ *    (i_0, ..., i_{m-1}) of an extent-n tensor is at sum_k i_k n^k.  For a
+ *    symmetric tensor this is also the row-major layout of shape (n,)*m.
+ *  - BCSS (§3.3, §4.3, §5.3): blocks of b^m entries; only blocks with sorted
+ *    block index s_0 <= ... <= s_{m-1} are stored, in colex order
+ *    (rank(s) = sum_k binom(s_k + k, k + 1); at b = 1, m = 2 this is the
+ *    packing order 0 1 3 / 2 4 / 5 of §3.3).  Each block is stored whole, in
+ *    dimensional order, padded with zeros when b does not divide n.
+ *  - Reentrant: sttsm and bcss_* may be called from several threads.
+ */
+#ifndef STTSM_H
+#define STTSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    STTSM_OK = 0,
+    STTSM_EINVAL = -1,    /* bad argument; nothing was launched               */
+    STTSM_ENOMEM = -2,    /* host/device allocation failed, or too big to fit */
+    STTSM_EHIP = -3,      /* a HIP runtime call failed                       */
+    STTSM_EAGAIN = -4,    /* serving: result not ready yet                    */
+    STTSM_ENOTFOUND = -5  /* serving: unknown or already fetched ticket      */
+} sttsm_status;
+
+typedef enum { STTSM_F32 = 0, STTSM_BF16 = 1, STTSM_F64 = 2 } sttsm_dtype;
+
+/*
+ * Precision forms of the block contractions.
+ *  FP32                 FP32 operands, temporaries and accumulation
+ *                       (v_mfma_f32_32x32x2_f32).  A, X: F32.
+ *  BF16                 A, X and the temporaries T^(k) rounded to bf16
+ *                       (nearest, ties to even), FP32 MFMA accumulation,
+ *                       temporaries stored bf16, C in FP32.  A, X: F32 or
+ *                       BF16 (same dtype for both).
+ *  BF16X3_FIRST_FP32    first contraction A -> T^(m-1) as three bf16
+ *                       products hi*hi + hi*lo + lo*hi of the split
+ *                       a = hi + lo (hi = bf16(a), lo = bf16(a - hi));
+ *                       later contractions FP32.  A, X: F32.
+ *  BF16X3_FIRST_BF16    split first contraction, T^(m-1) stored bf16, later
+ *                       contractions as in BF16.  A, X: F32.
+ * C is always F32.
+ */
+typedef enum {
+    STTSM_PREC_FP32 = 0,
+    STTSM_PREC_BF16 = 1,
+    STTSM_PREC_BF16X3_FIRST_FP32 = 2,
+    STTSM_PREC_BF16X3_FIRST_BF16 = 3
+} sttsm_prec;
+
+/* Shape of a symmetric tensor: order m (1..8), extent n (>= 1), block size
+ * b (>= 1), element type. */
+typedef struct {
+    int32_t m;
+    int64_t n;
+    int32_t b;
+    int32_t dtype; /* sttsm_dtype */
+} bcss_layout;
+
+/* binom(nbar + m - 1, m), the number of stored blocks (Table 1); -1 when
+ * m < 1, nbar < 1 or the count overflows int64. */
+int64_t bcss_num_blocks(int32_t m, int64_t nbar);
+
+/* Entries of the BCSS array, b^m * bcss_num_blocks(m, ceil(n/b)) (padded);
+ * -1 on a bad layout. */
+int64_t bcss_num_elems(const bcss_layout *L);
+
+/* Dense -> BCSS (§5.3).  Copies each sorted block of the dense tensor into its
+ * compact slot, bit for bit; entries beyond n are written as zero.  Only the
+ * sorted blocks of `dense` are read, so a non-symmetric input is packed
+ * without complaint (its other blocks are ignored).
+ * dense: n^m elements of L->dtype on the device; bcss: bcss_num_elems(L). */
+int bcss_pack(const bcss_layout *L, const void *dense, void *bcss, void *stream);
+
+/* BCSS -> dense.  Every dense block t is read from stored block sort(t) with
+ * its modes permuted by the stable argsort of t (App. B's meta-data tensor);
+ * padding is dropped.  Same buffer sizes as bcss_pack. */
+int bcss_unpack(const bcss_layout *L, const void *bcss, void *dense, void *stream);
+
+/* Symmetry-aware flop count of sttsm (Table 2, BCSS computation row, at the
+ * padded sizes nbar*bA and pbar*bC); -1 on bad layouts. */
+int64_t sttsm_flops(const bcss_layout *A, const bcss_layout *C);
+
+/* Bytes of device workspace sttsm needs for these shapes and precision
+ * (padded X panels and every temporary T^(m-1) .. T^(1)); 0 on bad input. */
+size_t sttsm_workspace_bytes(const bcss_layout *A, const bcss_layout *C, int32_t prec);
+
+/*
+ * C := [A; X, ..., X]  (§2.5), evaluated algorithm-by-blocks (§5.4, Figure 6)
+ * with the partial symmetry of the temporaries exploited (§6, Theorem 1):
+ *   T^(m-1) = A x_{m-1} X,  T^(k) = T^(k+1) x_k X,  C = T^(1) x_0 X,
+ * forming for each sorted tuple of C-block indices only the output blocks
+ * whose leading (symmetric) block indices are sorted.
+ *
+ * A      : BCSS of layout *A (A->n = n, A->b = bA), device.
+ * X      : p x n matrix on the device, entry (j, i) at X[j*rs_x + i*cs_x],
+ *          dtype A->dtype.  p = C->n.
+ * C      : BCSS of layout *C (C->b = bC, C->m = A->m, dtype F32), device;
+ *          fully overwritten (padding entries come out exactly zero).
+ * ws     : device workspace of at least sttsm_workspace_bytes(A, C, prec)
+ *          bytes, 256-byte aligned.  Its contents on return are the padded X
+ *          panels and the temporaries (see sttsm_workspace_temp).
+ * Entries of C inside blocks with repeated indices are computed one by one
+ * and may differ from their mirrored entries by rounding (§5.4).
+ */
+int sttsm(const bcss_layout *A, const void *A_dev, const void *X_dev, int64_t rs_x, int64_t cs_x,
+          const bcss_layout *C, void *C_dev, int32_t prec, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Where sttsm leaves temporary T^(k) (1 <= k <= m-1) inside the workspace.
+ * T^(k) has extent n in modes 0..k-1 (symmetric, Theorem 1) and p in modes
+ * k..m-1.  It is stored as [J][s][block]: J runs over sorted tuples
+ * (jbar_k <= ... <= jbar_{m-1}) of C-block indices in colex order
+ * (*num_jtuples of them), s over sorted tuples (ibar_0 <= ... <= ibar_{k-1})
+ * of A-block indices in colex order (*num_prefixes), and each block holds
+ * bA^k * bC^(m-k) entries in dimensional order.  *dtype is sttsm_dtype.
+ */
+int sttsm_workspace_temp(const bcss_layout *A, const bcss_layout *C, int32_t prec, int32_t k,
+                         size_t *byte_offset, int32_t *dtype, int64_t *num_jtuples,
+                         int64_t *num_prefixes, int64_t *block_elems);
+
+/*
+ * Inspection of the plan sttsm runs for these shapes (host only, launches
+ * nothing): for loop level `level` (0 forms T^(m-1), m-1 forms C) the number
+ * of row groups (sorted C-block tuple of the level x unique output prefix of
+ * the symmetric modes, Figure 6 with §6.3), of workgroup tasks, and the flops
+ * the level performs (its term of Table 2).
+ */
+int sttsm_plan_info(const bcss_layout *A, const bcss_layout *C, int32_t prec, int32_t level,
+                    int64_t *groups, int64_t *tasks, int64_t *flops);
+
+/*
+ * Per-level timing for measurement tools.  While enabled, sttsm records a
+ * pair of HIP events on its stream around each level's kernel launch (up to
+ * max_launches launches; later ones are counted as dropped).  The events are
+ * created here, not in sttsm.  sttsm_profile_read waits for the recorded
+ * events, writes the summed milliseconds and launch count per level
+ * (level_ms[d], level_launches[d], d < max_levels) and starts a new
+ * recording.  Not meant for concurrent sttsm calls from several threads.
+ */
+int sttsm_profile_enable(int32_t max_launches);
+int sttsm_profile_read(double *level_ms, int64_t *level_launches, int32_t max_levels, int64_t *dropped);
+int sttsm_profile_disable(void);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *sttsm_last_error(void);
+
+/* Library version string. */
+const char *sttsm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STTSM_H */

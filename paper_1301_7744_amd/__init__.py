@@ -1,0 +1,240 @@
+"""Python binding of libsttsm.so: symmetric tensor times same matrix on
+MI355X with tensors in Blocked Compact Symmetric Storage (BCSS).
+
+Argument marshalling only.  Every step runs in the library's HIP kernels;
+PyTorch supplies device memory and the current stream.  There is no CPU
+fallback: without the built library every call raises.
+
+Names follow the C ABI in include/sttsm.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsttsm.so")
+
+F32, BF16, F64 = 0, 1, 2
+PREC_FP32, PREC_BF16, PREC_BF16X3_FIRST_FP32, PREC_BF16X3_FIRST_BF16 = 0, 1, 2, 3
+PREC_NAMES = {"fp32": PREC_FP32, "bf16": PREC_BF16, "bf16x3_fp32": PREC_BF16X3_FIRST_FP32,
+              "bf16x3_bf16": PREC_BF16X3_FIRST_BF16}
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EAGAIN", -5: "ENOTFOUND"}
+
+
+class SttsmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int64), ("b", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """The loaded libsttsm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libsttsm.so is not built (run __graft_entry__.build() or "
+                          "python paper_1301_7744_amd/build.py); there is no fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    L = ctypes.POINTER(Layout)
+    vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    sig = {
+        "bcss_num_blocks": (i64, [i32, i64]),
+        "bcss_num_elems": (i64, [L]),
+        "bcss_pack": (ctypes.c_int, [L, vp, vp, vp]),
+        "bcss_unpack": (ctypes.c_int, [L, vp, vp, vp]),
+        "sttsm_flops": (i64, [L, L]),
+        "sttsm_workspace_bytes": (sz, [L, L, i32]),
+        "sttsm": (ctypes.c_int, [L, vp, vp, i64, i64, L, vp, i32, vp, sz, vp]),
+        "sttsm_workspace_temp": (ctypes.c_int, [L, L, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(i32),
+                                                ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "sttsm_plan_info": (ctypes.c_int, [L, L, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                           ctypes.POINTER(i64)]),
+        "sttsm_profile_enable": (ctypes.c_int, [i32]),
+        "sttsm_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32,
+                                              ctypes.POINTER(i64)]),
+        "sttsm_profile_disable": (ctypes.c_int, []),
+        "sttsm_last_error": (ctypes.c_char_p, []),
+        "sttsm_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return ["bcss_num_blocks", "bcss_num_elems", "bcss_pack", "bcss_unpack", "sttsm_flops",
+            "sttsm_workspace_bytes", "sttsm", "sttsm_workspace_temp", "sttsm_plan_info", "sttsm_profile_enable",
+            "sttsm_profile_read", "sttsm_profile_disable", "sttsm_last_error", "sttsm_version"]
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise SttsmError(rc, load().sttsm_last_error().decode())
+
+
+def layout(m: int, n: int, b: int, dtype: int = F32) -> Layout:
+    return Layout(int(m), int(n), int(b), int(dtype))
+
+
+def _torch_dtype_code(t) -> int:
+    import torch
+    return {torch.float32: F32, torch.bfloat16: BF16, torch.float64: F64}[t.dtype]
+
+
+def _torch_dtype(code: int):
+    import torch
+    return {F32: torch.float32, BF16: torch.bfloat16, F64: torch.float64}[code]
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+def _ptr(t) -> int:
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+# ------------------------------------------------------------------ queries
+def bcss_num_blocks(m: int, nbar: int) -> int:
+    return load().bcss_num_blocks(m, nbar)
+
+
+def bcss_num_elems(m: int, n: int, b: int, dtype: int = F32) -> int:
+    return load().bcss_num_elems(ctypes.byref(layout(m, n, b, dtype)))
+
+
+def sttsm_flops(m: int, n: int, p: int, bA: int, bC: int) -> int:
+    return load().sttsm_flops(ctypes.byref(layout(m, n, bA)), ctypes.byref(layout(m, p, bC)))
+
+
+def sttsm_workspace_bytes(m: int, n: int, p: int, bA: int, bC: int, prec: int = PREC_FP32,
+                          dtype: int = F32) -> int:
+    return load().sttsm_workspace_bytes(ctypes.byref(layout(m, n, bA, dtype)), ctypes.byref(layout(m, p, bC)), prec)
+
+
+def sttsm_workspace_temp(m: int, n: int, p: int, bA: int, bC: int, prec: int, k: int, dtype: int = F32) -> dict:
+    off, dt = ctypes.c_size_t(), ctypes.c_int32()
+    nj, npf, blk = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().sttsm_workspace_temp(ctypes.byref(layout(m, n, bA, dtype)), ctypes.byref(layout(m, p, bC)), prec,
+                                       k, ctypes.byref(off), ctypes.byref(dt), ctypes.byref(nj),
+                                       ctypes.byref(npf), ctypes.byref(blk)))
+    return dict(byte_offset=off.value, dtype=dt.value, num_jtuples=nj.value, num_prefixes=npf.value,
+                block_elems=blk.value)
+
+
+def sttsm_plan_info(m: int, n: int, p: int, bA: int, bC: int, prec: int, level: int, dtype: int = F32) -> dict:
+    g, t, f = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().sttsm_plan_info(ctypes.byref(layout(m, n, bA, dtype)), ctypes.byref(layout(m, p, bC)), prec,
+                                  level, ctypes.byref(g), ctypes.byref(t), ctypes.byref(f)))
+    return dict(groups=g.value, tasks=t.value, flops=f.value)
+
+
+# ------------------------------------------------------------------ operations
+def bcss_pack(dense, m: int, n: int, b: int, out=None, stream=None):
+    """Dense device tensor (n^m entries, dimensional order) -> BCSS tensor."""
+    import torch
+    dt = _torch_dtype_code(dense)
+    if dense.numel() != n ** m:
+        raise ValueError("dense tensor must hold n^m entries")
+    ne = bcss_num_elems(m, n, b, dt)
+    if out is None:
+        out = torch.empty(ne, dtype=dense.dtype, device=dense.device)
+    elif out.numel() < ne or out.dtype != dense.dtype:
+        raise ValueError("output too small or of the wrong dtype")
+    _check(load().bcss_pack(ctypes.byref(layout(m, n, b, dt)), _ptr(dense), _ptr(out), _stream(stream)))
+    return out
+
+
+def bcss_unpack(bcss, m: int, n: int, b: int, out=None, stream=None):
+    """BCSS device tensor -> dense (n^m entries, dimensional order)."""
+    import torch
+    dt = _torch_dtype_code(bcss)
+    if bcss.numel() < bcss_num_elems(m, n, b, dt):
+        raise ValueError("BCSS tensor too small")
+    if out is None:
+        out = torch.empty(n ** m, dtype=bcss.dtype, device=bcss.device)
+    elif out.numel() < n ** m or out.dtype != bcss.dtype:
+        raise ValueError("output too small or of the wrong dtype")
+    _check(load().bcss_unpack(ctypes.byref(layout(m, n, b, dt)), _ptr(bcss), _ptr(out), _stream(stream)))
+    return out
+
+
+def sttsm(A_bcss, X, m: int, n: int, p: int, bA: int, bC: int, prec: int = PREC_FP32, C=None, ws=None,
+          stream=None):
+    """C := [A; X, ..., X] with A and C in BCSS (X is p x n on the device).
+
+    Returns (C, ws); pass both back to reuse their memory."""
+    import torch
+    dt = _torch_dtype_code(A_bcss)
+    if X.dtype != A_bcss.dtype or X.dim() != 2 or tuple(X.shape) != (p, n):
+        raise ValueError("X must be a (p, n) tensor of A's dtype")
+    LA, LC = layout(m, n, bA, dt), layout(m, p, bC, F32)
+    if A_bcss.numel() < bcss_num_elems(m, n, bA, dt):
+        raise ValueError("A too small for its layout")
+    nc = bcss_num_elems(m, p, bC, F32)
+    if C is None:
+        C = torch.empty(nc, dtype=torch.float32, device=A_bcss.device)
+    elif C.numel() < nc or C.dtype != torch.float32:
+        raise ValueError("C too small or not float32")
+    wsb = load().sttsm_workspace_bytes(ctypes.byref(LA), ctypes.byref(LC), prec)
+    if wsb == 0:
+        raise SttsmError(-1, load().sttsm_last_error().decode())
+    if ws is None or ws.numel() < wsb:
+        ws = torch.empty(wsb, dtype=torch.uint8, device=A_bcss.device)
+    _check(load().sttsm(ctypes.byref(LA), _ptr(A_bcss), X.data_ptr(), X.stride(0), X.stride(1),
+                        ctypes.byref(LC), _ptr(C), prec, _ptr(ws), ws.numel(), _stream(stream)))
+    return C, ws
+
+
+def temporary(ws, m: int, n: int, p: int, bA: int, bC: int, prec: int, k: int, dtype: int = F32):
+    """View of T^(k) inside a workspace sttsm has filled: a tensor of shape
+    (num_jtuples, num_prefixes, block_elems), layout as in the header."""
+    info = sttsm_workspace_temp(m, n, p, bA, bC, prec, k, dtype)
+    tdt = _torch_dtype(info["dtype"])
+    esz = 4 if info["dtype"] == F32 else 2
+    count = info["num_jtuples"] * info["num_prefixes"] * info["block_elems"]
+    raw = ws[info["byte_offset"]: info["byte_offset"] + count * esz]
+    return raw.view(tdt).view(info["num_jtuples"], info["num_prefixes"], info["block_elems"])
+
+
+def profile_enable(max_launches: int = 4096):
+    _check(load().sttsm_profile_enable(max_launches))
+
+
+def profile_read(max_levels: int = 8):
+    """{level: (total_ms, launches)} recorded since enable / the last read."""
+    ms = (ctypes.c_double * max_levels)()
+    cnt = (ctypes.c_int64 * max_levels)()
+    dropped = ctypes.c_int64()
+    _check(load().sttsm_profile_read(ms, cnt, max_levels, ctypes.byref(dropped)))
+    out = {d: (ms[d], cnt[d]) for d in range(max_levels) if cnt[d]}
+    if dropped.value:
+        out["dropped"] = dropped.value
+    return out
+
+
+def profile_disable():
+    _check(load().sttsm_profile_disable())
+
+
+def version() -> str:
+    return load().sttsm_version().decode()

@@ -1,0 +1,313 @@
+// C ABI of libsttsm (declared in include/sttsm.h).
+#include "../../include/sttsm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace symt;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int dtype_size(int dt)
+{
+    switch (dt) {
+    case STTSM_F32: return 4;
+    case STTSM_BF16: return 2;
+    case STTSM_F64: return 8;
+    default: return 0;
+    }
+}
+
+bool layout_ok(const bcss_layout *L, std::string *why)
+{
+    if (!L) { *why = "null layout"; return false; }
+    if (L->m < 1 || L->m > kMaxOrder) { *why = "order m must be 1..8"; return false; }
+    if (L->n < 1) { *why = "n must be >= 1"; return false; }
+    if (L->b < 1) { *why = "block size b must be >= 1"; return false; }
+    if (!dtype_size(L->dtype)) { *why = "unknown dtype"; return false; }
+    if ((L->n + L->b - 1) / L->b > (1 << 20)) { *why = "too many blocks per mode"; return false; }
+    return true;
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Optional per-level timing: a pool of event pairs recorded around each
+// level's launch on the caller's stream, read back on request.
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> ev;      // 2 per slot
+    std::vector<int> level;          // level per used slot
+    size_t used = 0;
+    int64_t dropped = 0;
+};
+Profiler g_prof;
+
+// Returns the index of a free slot, or -1 (profiling off or pool exhausted).
+long prof_slot(int lvl)
+{
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    if (!g_prof.on) return -1;
+    if (g_prof.used >= g_prof.level.size()) {
+        ++g_prof.dropped;
+        return -1;
+    }
+    g_prof.level[g_prof.used] = lvl;
+    return (long)g_prof.used++;
+}
+
+// Validates an sttsm problem and returns its plan key.
+int make_key(const bcss_layout *A, const bcss_layout *C, int32_t prec, PlanKey *key)
+{
+    std::string why;
+    if (!layout_ok(A, &why)) return fail(STTSM_EINVAL, "A: " + why);
+    if (!layout_ok(C, &why)) return fail(STTSM_EINVAL, "C: " + why);
+    if (A->m != C->m) return fail(STTSM_EINVAL, "A and C must have the same order");
+    if (C->dtype != STTSM_F32) return fail(STTSM_EINVAL, "C must be F32");
+    if (prec < STTSM_PREC_FP32 || prec > STTSM_PREC_BF16X3_FIRST_BF16) return fail(STTSM_EINVAL, "unknown precision");
+    if (prec == STTSM_PREC_BF16) {
+        if (A->dtype != STTSM_F32 && A->dtype != STTSM_BF16) return fail(STTSM_EINVAL, "BF16 form needs F32 or BF16 A");
+    } else if (A->dtype != STTSM_F32) {
+        return fail(STTSM_EINVAL, "this precision form needs F32 A and X");
+    }
+    key->m = A->m;
+    key->n = A->n;
+    key->p = C->n;
+    key->bA = A->b;
+    key->bC = C->b;
+    key->prec = prec;
+    key->in_dtype = A->dtype == STTSM_F32 ? F32 : BF16;
+    return STTSM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sttsm_last_error(void) { return g_err.c_str(); }
+
+const char *sttsm_version(void) { return "sttsm 0.1 (gfx950)"; }
+
+int64_t bcss_num_blocks(int32_t m, int64_t nbar)
+{
+    if (m < 1 || nbar < 1) return -1;
+    return binom(nbar + m - 1, m);
+}
+
+int64_t bcss_num_elems(const bcss_layout *L)
+{
+    std::string why;
+    if (!layout_ok(L, &why)) return -1;
+    const int64_t nb = bcss_num_blocks(L->m, (L->n + L->b - 1) / L->b);
+    if (nb < 0) return -1;
+    __int128 e = nb;
+    for (int j = 0; j < L->m; ++j) {
+        e *= L->b;
+        if (e > ((__int128)1 << 62)) return -1;
+    }
+    return (int64_t)e;
+}
+
+int bcss_pack(const bcss_layout *L, const void *dense, void *bcss, void *stream)
+{
+    std::string why;
+    if (!layout_ok(L, &why)) return fail(STTSM_EINVAL, why);
+    if (!dense || !bcss) return fail(STTSM_EINVAL, "null buffer");
+    const int64_t ne = bcss_num_elems(L);
+    if (ne < 0) return fail(STTSM_EINVAL, "BCSS size overflows");
+    const int nbar = (int)((L->n + L->b - 1) / L->b);
+    const MetaTable *T = meta_get(L->m, nbar, L->b, &why);
+    if (!T) return fail(STTSM_ENOMEM, why);
+    if (launch_pack(dtype_size(L->dtype), dense, bcss, L->m, L->n, L->b, bcss_num_blocks(L->m, nbar),
+                    T->d_tuples, as_stream(stream)))
+        return fail(STTSM_EHIP, std::string("pack launch failed: ") + hipGetErrorString(hipGetLastError()));
+    return STTSM_OK;
+}
+
+int bcss_unpack(const bcss_layout *L, const void *bcss, void *dense, void *stream)
+{
+    std::string why;
+    if (!layout_ok(L, &why)) return fail(STTSM_EINVAL, why);
+    if (!dense || !bcss) return fail(STTSM_EINVAL, "null buffer");
+    const int nbar = (int)((L->n + L->b - 1) / L->b);
+    const MetaTable *T = meta_get(L->m, nbar, L->b, &why);
+    if (!T) return fail(STTSM_ENOMEM, why);
+    if (launch_unpack(dtype_size(L->dtype), bcss, dense, L->m, L->n, L->b, nbar, T->d_rank, T->d_perm,
+                      T->d_perm_strides, as_stream(stream)))
+        return fail(STTSM_EHIP, std::string("unpack launch failed: ") + hipGetErrorString(hipGetLastError()));
+    return STTSM_OK;
+}
+
+int64_t sttsm_flops(const bcss_layout *A, const bcss_layout *C)
+{
+    std::string why;
+    if (!layout_ok(A, &why) || !layout_ok(C, &why) || A->m != C->m) return -1;
+    const int64_t nbar = (A->n + A->b - 1) / A->b, pbar = (C->n + C->b - 1) / C->b;
+    const int m = A->m;
+    __int128 total = 0;
+    for (int d = 0; d < m; ++d) {
+        const int64_t jt = binom(pbar + d, d + 1), pf = binom(nbar + m - d - 2, m - d - 1);
+        if (jt < 0 || pf < 0) return -1;
+        __int128 t = (__int128)jt * pf;
+        for (int i = 0; i < m - d; ++i) t *= A->b;
+        for (int i = 0; i < d + 1; ++i) t *= C->b;
+        total += t;
+        if (total > ((__int128)1 << 60)) return -1;
+    }
+    total *= 2 * nbar;
+    return (int64_t)total;
+}
+
+size_t sttsm_workspace_bytes(const bcss_layout *A, const bcss_layout *C, int32_t prec)
+{
+    PlanKey key;
+    if (make_key(A, C, prec, &key) != STTSM_OK) return 0;
+    Plan P;
+    std::string why;
+    if (!plan_build_host(key, &P, &why)) {
+        g_err = why;
+        return 0;
+    }
+    return P.ws_bytes;
+}
+
+int sttsm_workspace_temp(const bcss_layout *A, const bcss_layout *C, int32_t prec, int32_t k, size_t *byte_offset,
+                         int32_t *dtype, int64_t *num_jtuples, int64_t *num_prefixes, int64_t *block_elems)
+{
+    PlanKey key;
+    int rc = make_key(A, C, prec, &key);
+    if (rc != STTSM_OK) return rc;
+    if (k < 1 || k >= A->m) return fail(STTSM_EINVAL, "k must be 1..m-1");
+    Plan P;
+    std::string why;
+    if (!plan_build_host(key, &P, &why)) return fail(STTSM_EINVAL, why);
+    if (byte_offset) *byte_offset = (size_t)P.temp_off[k];
+    if (dtype) *dtype = P.temp_dtype[k] == F32 ? STTSM_F32 : STTSM_BF16;
+    if (num_jtuples) *num_jtuples = P.temp_jtuples[k];
+    if (num_prefixes) *num_prefixes = P.temp_prefixes[k];
+    if (block_elems) *block_elems = P.temp_block[k];
+    return STTSM_OK;
+}
+
+int sttsm_plan_info(const bcss_layout *A, const bcss_layout *C, int32_t prec, int32_t level, int64_t *groups,
+                    int64_t *tasks, int64_t *flops)
+{
+    PlanKey key;
+    int rc = make_key(A, C, prec, &key);
+    if (rc != STTSM_OK) return rc;
+    if (level < 0 || level >= A->m) return fail(STTSM_EINVAL, "level must be 0..m-1");
+    Plan P;
+    std::string why;
+    if (!plan_build_host(key, &P, &why)) return fail(STTSM_EINVAL, why);
+    const StagePlan &S = P.stages[level];
+    if (groups) *groups = (int64_t)S.groups.size();
+    if (tasks) *tasks = (int64_t)S.tasks.size();
+    if (flops) *flops = S.flops;
+    return STTSM_OK;
+}
+
+int sttsm(const bcss_layout *A, const void *A_dev, const void *X_dev, int64_t rs_x, int64_t cs_x,
+          const bcss_layout *C, void *C_dev, int32_t prec, void *ws, size_t ws_bytes, void *stream)
+{
+    PlanKey key;
+    int rc = make_key(A, C, prec, &key);
+    if (rc != STTSM_OK) return rc;
+    if (!A_dev || !X_dev || !C_dev) return fail(STTSM_EINVAL, "null buffer");
+    if (((uintptr_t)ws & 255) != 0) return fail(STTSM_EINVAL, "workspace must be 256-byte aligned");
+    std::string why;
+    const Plan *P = plan_get(key, &why);
+    if (!P) return fail(STTSM_ENOMEM, why);
+    if (ws_bytes < P->ws_bytes || (!ws && P->ws_bytes)) return fail(STTSM_EINVAL, "workspace too small");
+    hipStream_t s = as_stream(stream);
+    char *w = (char *)ws;
+    float *x32 = P->xp_off[0] >= 0 ? (float *)(w + P->xp_off[0]) : nullptr;
+    uint16_t *xhi = P->xp_off[1] >= 0 ? (uint16_t *)(w + P->xp_off[1]) : nullptr;
+    uint16_t *xlo = P->xp_off[2] >= 0 ? (uint16_t *)(w + P->xp_off[2]) : nullptr;
+    if (launch_prep_x(dtype_size(A->dtype), X_dev, rs_x, cs_x, P->p, P->n, P->Ppad, P->Kx, x32, xhi, xlo, s))
+        return fail(STTSM_EHIP, std::string("X panel launch failed: ") + hipGetErrorString(hipGetLastError()));
+    const void *slot_ptr[3] = {x32, xhi, xlo};
+    for (const StagePlan &S : P->stages) {
+        StageArgs a = S.args;
+        a.in = S.in_ws < 0 ? A_dev : (const void *)(w + S.in_ws);
+        a.out = S.out_ws < 0 ? C_dev : (void *)(w + S.out_ws);
+        a.xp = slot_ptr[S.xp_slot];
+        a.xp_lo = S.xp_lo_slot >= 0 ? slot_ptr[S.xp_lo_slot] : nullptr;
+        const long slot = prof_slot(S.d);
+        if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot], s);
+        if (launch_stage(a, S.compute, S.tile.MT, S.d == 0, s))
+            return fail(STTSM_EHIP, std::string("stage launch failed: ") + hipGetErrorString(hipGetLastError()));
+        if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot + 1], s);
+    }
+    return STTSM_OK;
+}
+
+int sttsm_profile_enable(int32_t max_launches)
+{
+    if (max_launches < 1 || max_launches > (1 << 16)) return fail(STTSM_EINVAL, "max_launches must be 1..65536");
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    for (hipEvent_t e : g_prof.ev) (void)hipEventDestroy(e);
+    g_prof.ev.assign(2 * (size_t)max_launches, nullptr);
+    for (auto &e : g_prof.ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            g_prof.ev.clear();
+            g_prof.level.clear();
+            g_prof.on = false;
+            return fail(STTSM_EHIP, "hipEventCreate failed");
+        }
+    g_prof.level.assign(max_launches, -1);
+    g_prof.used = 0;
+    g_prof.dropped = 0;
+    g_prof.on = true;
+    return STTSM_OK;
+}
+
+int sttsm_profile_read(double *level_ms, int64_t *level_launches, int32_t max_levels, int64_t *dropped)
+{
+    if (!level_ms || !level_launches || max_levels < 1) return fail(STTSM_EINVAL, "bad output arrays");
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    for (int i = 0; i < max_levels; ++i) { level_ms[i] = 0.0; level_launches[i] = 0; }
+    for (size_t i = 0; i < g_prof.used; ++i) {
+        const int lvl = g_prof.level[i];
+        if (hipEventSynchronize(g_prof.ev[2 * i + 1]) != hipSuccess) return fail(STTSM_EHIP, "event wait failed");
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]) != hipSuccess)
+            return fail(STTSM_EHIP, "hipEventElapsedTime failed");
+        if (lvl >= 0 && lvl < max_levels) {
+            level_ms[lvl] += ms;
+            level_launches[lvl] += 1;
+        }
+    }
+    if (dropped) *dropped = g_prof.dropped;
+    g_prof.used = 0;
+    g_prof.dropped = 0;
+    return STTSM_OK;
+}
+
+int sttsm_profile_disable(void)
+{
+    std::lock_guard<std::mutex> lock(g_prof.mu);
+    for (hipEvent_t e : g_prof.ev) (void)hipEventDestroy(e);
+    g_prof.ev.clear();
+    g_prof.level.clear();
+    g_prof.used = 0;
+    g_prof.on = false;
+    return STTSM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,507 @@
+// gfx950 kernels of libsttsm: BCSS pack/unpack, X panel preparation, and the
+// block-contraction stage kernel on MFMA.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace symt {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16;
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+// fp32 -> bf16, round to nearest, ties to even (finite inputs).
+__device__ __forceinline__ u16 f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (u16)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(u16 h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// ------------------------------------------------------------------ pack/unpack
+// One thread per BCSS entry: block r (colex), local offset l (dimensional
+// order).  Reads the dense entry, or writes zero beyond n.
+template <class E>
+__global__ void bcss_pack_kernel(const E *__restrict__ dense, E *__restrict__ bcss, int m, int64_t n,
+                                 int b, int64_t bm, int64_t total, const int32_t *__restrict__ tuples)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / bm;
+        int64_t l = e - r * bm;
+        int64_t off = 0, npow = 1;
+        bool ok = true;
+        for (int j = 0; j < m; ++j) {
+            const int64_t lj = l % b;
+            l /= b;
+            const int64_t ij = (int64_t)tuples[r * m + j] * b + lj;
+            ok = ok && ij < n;
+            off += ij * npow;
+            npow *= n;
+        }
+        bcss[e] = ok ? dense[off] : E(0);
+    }
+}
+
+// One thread per dense entry: its block t and local index l; the meta-data
+// tensor gives the stored block sort(t) and the permuted strides.
+template <class E>
+__global__ void bcss_unpack_kernel(const E *__restrict__ bcss, E *__restrict__ dense, int m, int64_t n,
+                                   int b, int nbar, int64_t bm, int64_t total, const int64_t *__restrict__ rank,
+                                   const int32_t *__restrict__ perm, const int32_t *__restrict__ pstr)
+{
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < total;
+         f += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = f;
+        int64_t meta = 0, mpow = 1;
+        int32_t loc[kMaxOrder];
+        for (int j = 0; j < m; ++j) {
+            const int64_t ij = r % n;
+            r /= n;
+            const int64_t tj = ij / b;
+            loc[j] = (int32_t)(ij - tj * b);
+            meta += tj * mpow;
+            mpow *= nbar;
+        }
+        const int32_t *ps = pstr + (int64_t)perm[meta] * m;
+        int64_t off = rank[meta] * bm;
+        for (int j = 0; j < m; ++j) off += (int64_t)loc[j] * ps[j];
+        dense[f] = bcss[off];
+    }
+}
+
+template <class E>
+static int launch_pack_t(const void *dense, void *bcss, int m, int64_t n, int b, int64_t bm, int64_t total,
+                         const int32_t *tuples, hipStream_t s)
+{
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 1 << 20);
+    hipLaunchKernelGGL(bcss_pack_kernel<E>, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, s,
+                       (const E *)dense, (E *)bcss, m, n, b, bm, total, tuples);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <class E>
+static int launch_unpack_t(const void *bcss, void *dense, int m, int64_t n, int b, int nbar, int64_t bm,
+                           int64_t total, const int64_t *rank, const int32_t *perm, const int32_t *pstr,
+                           hipStream_t s)
+{
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 1 << 20);
+    hipLaunchKernelGGL(bcss_unpack_kernel<E>, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, s,
+                       (const E *)bcss, (E *)dense, m, n, b, nbar, bm, total, rank, perm, pstr);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_pack(int esize, const void *dense, void *bcss, int m, int64_t n, int b, int64_t nblocks,
+                const int32_t *d_tuples, hipStream_t s)
+{
+    int64_t bm = 1;
+    for (int j = 0; j < m; ++j) bm *= b;
+    const int64_t total = bm * nblocks;
+    if (esize == 2) return launch_pack_t<uint16_t>(dense, bcss, m, n, b, bm, total, d_tuples, s);
+    if (esize == 4) return launch_pack_t<uint32_t>(dense, bcss, m, n, b, bm, total, d_tuples, s);
+    if (esize == 8) return launch_pack_t<uint64_t>(dense, bcss, m, n, b, bm, total, d_tuples, s);
+    return -1;
+}
+
+int launch_unpack(int esize, const void *bcss, void *dense, int m, int64_t n, int b, int nbar,
+                  const int64_t *d_rank, const int32_t *d_perm, const int32_t *d_pstr, hipStream_t s)
+{
+    int64_t bm = 1, total = 1;
+    for (int j = 0; j < m; ++j) { bm *= b; total *= n; }
+    if (esize == 2) return launch_unpack_t<uint16_t>(bcss, dense, m, n, b, nbar, bm, total, d_rank, d_perm, d_pstr, s);
+    if (esize == 4) return launch_unpack_t<uint32_t>(bcss, dense, m, n, b, nbar, bm, total, d_rank, d_perm, d_pstr, s);
+    if (esize == 8) return launch_unpack_t<uint64_t>(bcss, dense, m, n, b, nbar, bm, total, d_rank, d_perm, d_pstr, s);
+    return -1;
+}
+
+// ------------------------------------------------------------------ X panels
+// Xp[j][i] = X(j, i) for j < p, i < n, zero elsewhere; rows of Kx entries.
+// Slot 0 fp32, slot 1 bf16(x), slot 2 bf16(x - bf16(x)).
+template <class E>
+__global__ void prep_x_kernel(const E *__restrict__ X, int64_t rs, int64_t cs, int64_t p, int64_t n,
+                              int64_t Ppad, int64_t Kx, float *__restrict__ x32, u16 *__restrict__ xhi,
+                              u16 *__restrict__ xlo)
+{
+    const int64_t total = Ppad * Kx;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = e / Kx, i = e - j * Kx;
+        float v = 0.f;
+        if (j < p && i < n) {
+            if constexpr (sizeof(E) == 4) v = __uint_as_float(X[j * rs + i * cs]);
+            else v = bf2f(X[j * rs + i * cs]);
+        }
+        if (x32) x32[e] = v;
+        const u16 h = f2bf(v);
+        if (xhi) xhi[e] = h;
+        if (xlo) xlo[e] = f2bf(v - bf2f(h));
+    }
+}
+
+int launch_prep_x(int esize, const void *X, int64_t rs, int64_t cs, int64_t p, int64_t n, int64_t Ppad,
+                  int64_t Kx, float *x32, uint16_t *xhi, uint16_t *xlo, hipStream_t s)
+{
+    const int64_t total = Ppad * Kx;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 1 << 16));
+    if (esize == 4)
+        hipLaunchKernelGGL(prep_x_kernel<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s, (const uint32_t *)X,
+                           rs, cs, p, n, Ppad, Kx, x32, xhi, xlo);
+    else if (esize == 2)
+        hipLaunchKernelGGL(prep_x_kernel<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, s, (const uint16_t *)X,
+                           rs, cs, p, n, Ppad, Kx, x32, xhi, xlo);
+    else
+        return -1;
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ------------------------------------------------------------------ stage kernel
+//
+// One workgroup (4 waves) computes an MT x NT tile of one row group's GEMM
+//   Out[mm][nn] = sum_k In[mm][k] * X[nn][k],
+// where mm runs over the entries of an input block without the contracted
+// mode k, nn = jbar*bC + jj over the output C-block index of mode k, and
+// k = ibar*bA + lk over the contracted mode.  In[mm][k] is entry (mm, lk) of
+// the logical input block (s, ibar), read from the stored block sort(s, ibar)
+// through the strides of insertion position q: the permutation is applied
+// while staging, so no permuted copy is ever formed.
+//
+// Both operands are staged in LDS as [row][k] with k contiguous (row stride
+// KT + pad), double buffered, with the next chunk's global loads in flight
+// while the MFMAs consume the current one.
+template <int CMP>
+struct CmpTraits;
+template <>
+struct CmpTraits<CMP_FP32> {
+    static constexpr int KT = 16, LROW = 20, VK = 4;   // floats per row, k per vector
+    typedef float L;
+};
+template <>
+struct CmpTraits<CMP_BF16> {
+    static constexpr int KT = 32, LROW = 40, VK = 8;   // bf16 per row
+    typedef u16 L;
+};
+template <>
+struct CmpTraits<CMP_X3> {
+    static constexpr int KT = 32, LROW = 40, VK = 8;
+    typedef u16 L;
+};
+
+template <int CMP, int MT, int NT, int WM, int WN, bool B_IS_IN, bool FIRST>
+__global__ __launch_bounds__(256) void stage_kernel(const StageArgs a)
+{
+    using Tr = CmpTraits<CMP>;
+    using L = typename Tr::L;
+    constexpr int KT = Tr::KT, LROW = Tr::LROW, VK = Tr::VK;
+    constexpr bool SPLIT = CMP == CMP_X3;
+    constexpr int NL = SPLIT ? 2 : 1;            // LDS planes (hi, lo)
+    constexpr int WTM = MT / WM, WTN = NT / WN;  // wave tile
+    constexpr int TM = WTM / 32, TN = WTN / 32;  // 32x32 subtiles per wave
+    static_assert(WM * WN == 4 && TM >= 1 && TN >= 1, "tile shape");
+    constexpr int IN_VECS = MT * KT / VK;        // vectors of VK k-values per In chunk
+    constexpr int X_VECS = NT * KT / VK;
+    constexpr int IN_PER_T = (IN_VECS + 255) / 256;
+    constexpr int X_PER_T = (X_VECS + 255) / 256;
+
+    __shared__ __attribute__((aligned(16))) L s_in[NL][2][MT * LROW];
+    __shared__ __attribute__((aligned(16))) L s_x[NL][2][NT * LROW];
+    __shared__ int32_t s_mpart[kMaxOrder][MT];   // input offset of row mm, per insertion position
+    __shared__ int32_t s_opart[MT];              // output offset of row mm (-1: beyond Mblk)
+    __shared__ int64_t s_npart[NT];              // output offset of column nn (-1: beyond N)
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const Task task = a.tasks[blockIdx.x];
+    const GroupDesc g = a.groups[task.group];
+    const int m0 = task.mt * MT, n0 = task.nt * NT;
+    const int Nvalid = g.jcount * a.bC;
+
+    // Row and column offset tables of this tile.
+    for (int mm = tid; mm < MT; mm += 256) {
+        const int mg = m0 + mm;
+        if (mg < a.Mblk) {
+            int r = mg;
+            int dig[kMaxOrder];
+            for (int i = 0; i < a.m - 1; ++i) { dig[i] = r % a.mrad[i]; r /= a.mrad[i]; }
+            int op = 0;
+            for (int i = 0; i < a.m - 1; ++i) op += dig[i] * a.os[a.mmode[i]];
+            s_opart[mm] = op;
+            for (int q = 0; q <= a.k; ++q) {
+                int ip = 0;
+                for (int i = 0; i < a.m - 1; ++i) ip += dig[i] * a.sq[q][a.mmode[i]];
+                s_mpart[q][mm] = ip;
+            }
+        } else {
+            s_opart[mm] = -1;
+            for (int q = 0; q <= a.k; ++q) s_mpart[q][mm] = -1;
+        }
+    }
+    for (int nn = tid; nn < NT; nn += 256) {
+        const int ng = n0 + nn;
+        if (ng < Nvalid) {
+            const int jb = ng / a.bC, jj = ng - jb * a.bC;
+            s_npart[nn] = g.out_base + (int64_t)jb * g.out_jstride + (int64_t)jj * a.os[a.k];
+        } else {
+            s_npart[nn] = -1;
+        }
+    }
+
+    // Per-thread staging assignment (fixed across chunks).
+    // In: vector v -> row mm = v % MT, k-vector kv = v / MT.
+    // X : vector v -> row nn = v / (KT/VK), kv = v % (KT/VK).
+    float in_f[IN_PER_T][VK];   // staged input values (fp32; bf16 inputs widened)
+    f32x4 x_f32[X_PER_T];       // staged X (fp32 compute)
+    u16x8 x_hi[X_PER_T], x_lo[X_PER_T];
+
+    const float *in32 = (const float *)a.in;
+    const u16 *in16 = (const u16 *)a.in;
+    const InEntry *row = a.in_tab + g.in_row;
+
+    __syncthreads();
+
+    auto load_chunk = [&](int c) {
+        const int blk0 = (c / a.chunks_per_blk) * a.chunk_blocks;
+        const int lk0 = (c % a.chunks_per_blk) * a.chunk_k;
+        // valid k values of this chunk (a prefix of 0..KT-1)
+        int kvalid;
+        if (a.chunk_blocks > 1) kvalid = min(a.chunk_blocks, a.nbar - blk0) * a.bA;
+        else kvalid = min(a.chunk_k, a.bA - lk0);
+        const int kstart = blk0 * a.bA + lk0;
+#pragma unroll
+        for (int t = 0; t < IN_PER_T; ++t) {
+            const int v = tid + t * 256;
+            const int mm = v % MT, kv = v / MT;
+#pragma unroll
+            for (int e = 0; e < VK; ++e) in_f[t][e] = 0.f;
+            if (v < IN_VECS && s_mpart[0][mm] >= 0) {
+#pragma unroll
+                for (int e = 0; e < VK; ++e) {
+                    const int kk = kv * VK + e;
+                    if (kk < kvalid) {
+                        const int gi = kk / a.chunk_k;
+                        const int lk = lk0 + (kk - gi * a.chunk_k);
+                        const InEntry ie = row[blk0 + gi];
+                        const int64_t off = ie.off + s_mpart[ie.q][mm] + (int64_t)lk * a.sq[ie.q][a.k];
+                        in_f[t][e] = a.in_f32 ? in32[off] : bf2f(in16[off]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < X_PER_T; ++t) {
+            const int v = tid + t * 256;
+            const int nn = v / (KT / VK), kv = v % (KT / VK);
+            const int ng = n0 + nn;
+            const bool rowok = v < X_VECS && ng < Nvalid;
+            const int64_t base = (int64_t)ng * a.Kx + kstart + kv * VK;
+            if constexpr (CMP == CMP_FP32) {
+                const float *xp = (const float *)a.xp;
+                f32x4 val = {0.f, 0.f, 0.f, 0.f};
+                if (rowok) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (kv * 4 + e < kvalid) val[e] = xp[base + e];
+                }
+                x_f32[t] = val;
+            } else {
+                const u16 *xh = (const u16 *)a.xp;
+                const u16 *xl = (const u16 *)a.xp_lo;
+                u16x8 h = {0, 0, 0, 0, 0, 0, 0, 0}, l = {0, 0, 0, 0, 0, 0, 0, 0};
+                if (rowok) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        if (kv * 8 + e < kvalid) {
+                            h[e] = xh[base + e];
+                            if constexpr (SPLIT) l[e] = xl[base + e];
+                        }
+                    }
+                }
+                x_hi[t] = h;
+                if constexpr (SPLIT) x_lo[t] = l;
+            }
+        }
+    };
+
+    auto store_chunk = [&](int buf) {
+#pragma unroll
+        for (int t = 0; t < IN_PER_T; ++t) {
+            const int v = tid + t * 256;
+            if (v >= IN_VECS) break;
+            const int mm = v % MT, kv = v / MT;
+            if constexpr (CMP == CMP_FP32) {
+                f32x4 val = {in_f[t][0], in_f[t][1], in_f[t][2], in_f[t][3]};
+                *(f32x4 *)&s_in[0][buf][mm * LROW + kv * 4] = val;
+            } else {
+                u16x8 h, l;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float f = in_f[t][e];
+                    const u16 hb = f2bf(f);
+                    h[e] = hb;
+                    if constexpr (SPLIT) l[e] = f2bf(f - bf2f(hb));
+                }
+                *(u16x8 *)&s_in[0][buf][mm * LROW + kv * 8] = h;
+                if constexpr (SPLIT) *(u16x8 *)&s_in[NL - 1][buf][mm * LROW + kv * 8] = l;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < X_PER_T; ++t) {
+            const int v = tid + t * 256;
+            if (v >= X_VECS) break;
+            const int nn = v / (KT / VK), kv = v % (KT / VK);
+            if constexpr (CMP == CMP_FP32) {
+                *(f32x4 *)&s_x[0][buf][nn * LROW + kv * 4] = x_f32[t];
+            } else {
+                *(u16x8 *)&s_x[0][buf][nn * LROW + kv * 8] = x_hi[t];
+                if constexpr (SPLIT) *(u16x8 *)&s_x[NL - 1][buf][nn * LROW + kv * 8] = x_lo[t];
+            }
+        }
+    };
+
+    f32x16 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const int r32 = lane & 31, half = lane >> 5;
+    load_chunk(0);
+    for (int c = 0; c < a.nchunks; ++c) {
+        const int buf = c & 1;
+        store_chunk(buf);
+        __syncthreads();
+        if (c + 1 < a.nchunks) load_chunk(c + 1);
+        if constexpr (CMP == CMP_FP32) {
+#pragma unroll
+            for (int kg = 0; kg < KT / 8; ++kg) {
+                f32x4 va[TM], vb[TN];
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+                    va[i] = *(const f32x4 *)&s_in[0][buf][(wm * WTM + i * 32 + r32) * LROW + kg * 8 + half * 4];
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    vb[j] = *(const f32x4 *)&s_x[0][buf][(wn * WTN + j * 32 + r32) * LROW + kg * 8 + half * 4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) {
+                            if constexpr (B_IS_IN)
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(vb[j][t], va[i][t], acc[i][j], 0, 0, 0);
+                            else
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(va[i][t], vb[j][t], acc[i][j], 0, 0, 0);
+                        }
+            }
+        } else {
+#pragma unroll
+            for (int kg = 0; kg < KT / 16; ++kg) {
+                bf16x8 ha[TM], hb[TN], la[TM], lb[TN];
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const int o = (wm * WTM + i * 32 + r32) * LROW + kg * 16 + half * 8;
+                    ha[i] = __builtin_bit_cast(bf16x8, *(const u16x8 *)&s_in[0][buf][o]);
+                    if constexpr (SPLIT) la[i] = __builtin_bit_cast(bf16x8, *(const u16x8 *)&s_in[NL - 1][buf][o]);
+                }
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int o = (wn * WTN + j * 32 + r32) * LROW + kg * 16 + half * 8;
+                    hb[j] = __builtin_bit_cast(bf16x8, *(const u16x8 *)&s_x[0][buf][o]);
+                    if constexpr (SPLIT) lb[j] = __builtin_bit_cast(bf16x8, *(const u16x8 *)&s_x[NL - 1][buf][o]);
+                }
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) {
+                        if constexpr (B_IS_IN) {
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hb[j], ha[i], acc[i][j], 0, 0, 0);
+                            if constexpr (SPLIT) {
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lb[j], ha[i], acc[i][j], 0, 0, 0);
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hb[j], la[i], acc[i][j], 0, 0, 0);
+                            }
+                        } else {
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ha[i], hb[j], acc[i][j], 0, 0, 0);
+                            if constexpr (SPLIT) {
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ha[i], lb[j], acc[i][j], 0, 0, 0);
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(la[i], hb[j], acc[i][j], 0, 0, 0);
+                            }
+                        }
+                    }
+            }
+        }
+    }
+
+    // Epilogue: D[row][col] of a 32x32 subtile sits in lane col = lane%32,
+    // register r at row 8*(r/4) + 4*(lane/32) + r%4.
+    float *out32 = (float *)a.out;
+    u16 *out16 = (u16 *)a.out;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int rowi = 8 * (r >> 2) + 4 * half + (r & 3);
+                int mm, nn;
+                if constexpr (B_IS_IN) {
+                    mm = wm * WTM + i * 32 + r32;
+                    nn = wn * WTN + j * 32 + rowi;
+                } else {
+                    mm = wm * WTM + i * 32 + rowi;
+                    nn = wn * WTN + j * 32 + r32;
+                }
+                const int op = s_opart[mm];
+                const int64_t np = s_npart[nn];
+                if (op >= 0 && np >= 0) {
+                    const int64_t o = np + op;
+                    if (a.out_f32) out32[o] = acc[i][j][r];
+                    else out16[o] = f2bf(acc[i][j][r]);
+                }
+            }
+}
+
+// FIRST marks the level that reads A; it is a separate instantiation so that
+// profilers report the first contraction on its own.
+template <int CMP, bool B_IS_IN, bool FIRST>
+static int launch_stage_cmp(const StageArgs &a, int MT, hipStream_t s)
+{
+    const dim3 grid((unsigned)a.ntasks), block(256);
+    switch (MT) {
+    case 256: hipLaunchKernelGGL((stage_kernel<CMP, 256, 64, 4, 1, B_IS_IN, FIRST>), grid, block, 0, s, a); break;
+    case 128: hipLaunchKernelGGL((stage_kernel<CMP, 128, 64, 2, 2, B_IS_IN, FIRST>), grid, block, 0, s, a); break;
+    case 64: hipLaunchKernelGGL((stage_kernel<CMP, 64, 64, 2, 2, B_IS_IN, FIRST>), grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((stage_kernel<CMP, 32, 128, 1, 4, B_IS_IN, FIRST>), grid, block, 0, s, a); break;
+    default: return -1;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int CMP>
+static int launch_stage_c(const StageArgs &a, int MT, bool first, hipStream_t s)
+{
+    const bool b_in = a.k != 0;   // output contiguous along the block rows unless mode 0 is contracted
+    if (first) return b_in ? launch_stage_cmp<CMP, true, true>(a, MT, s) : launch_stage_cmp<CMP, false, true>(a, MT, s);
+    return b_in ? launch_stage_cmp<CMP, true, false>(a, MT, s) : launch_stage_cmp<CMP, false, false>(a, MT, s);
+}
+
+int launch_stage(const StageArgs &a, int compute, int MT, bool first, hipStream_t s)
+{
+    if (a.ntasks <= 0) return 0;
+    if (compute == CMP_FP32) return launch_stage_c<CMP_FP32>(a, MT, first, s);
+    if (compute == CMP_BF16) return launch_stage_c<CMP_BF16>(a, MT, first, s);
+    if (compute == CMP_X3) {   // the split form only ever runs the first level
+        if (!first) return -1;
+        return a.k != 0 ? launch_stage_cmp<CMP_X3, true, true>(a, MT, s) : launch_stage_cmp<CMP_X3, false, true>(a, MT, s);
+    }
+    return -1;
+}
+
+}  // namespace symt

@@ -1,0 +1,426 @@
+// Host plan for BCSS sttsm (see plan.hpp).
+#include "plan.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
+
+namespace symt {
+
+int64_t binom(int64_t n, int64_t k)
+{
+    if (n < 0 || k < 0 || k > n) return (n >= 0 && k >= 0) ? 0 : -1;
+    if (k > n - k) k = n - k;
+    __int128 r = 1;
+    for (int64_t i = 1; i <= k; ++i) {
+        r = r * (n - k + i) / i;   // exact: r is binom(n-k+i, i) after this step
+        if (r > (__int128)INT64_MAX) return -1;
+    }
+    return (int64_t)r;
+}
+
+int64_t colex_rank(const int32_t *s, int len)
+{
+    int64_t r = 0;
+    for (int i = 0; i < len; ++i) r += binom((int64_t)s[i] + i, i + 1);
+    return r;
+}
+
+std::vector<int32_t> sorted_tuples(int len, int N)
+{
+    std::vector<int32_t> out;
+    if (len == 0) return out;
+    std::vector<int32_t> s(len, 0);
+    for (;;) {
+        out.insert(out.end(), s.begin(), s.end());
+        // colex successor: increment the first entry that can grow while the
+        // tuple stays sorted; reset the entries before it to zero
+        int i = 0;
+        while (i < len && s[i] >= (i + 1 < len ? s[i + 1] : N - 1)) ++i;
+        if (i == len) break;
+        ++s[i];
+        for (int l = 0; l < i; ++l) s[l] = 0;
+    }
+    return out;
+}
+
+bool PlanKey::operator<(const PlanKey &o) const
+{
+    if (m != o.m) return m < o.m;
+    if (n != o.n) return n < o.n;
+    if (p != o.p) return p < o.p;
+    if (bA != o.bA) return bA < o.bA;
+    if (bC != o.bC) return bC < o.bC;
+    if (prec != o.prec) return prec < o.prec;
+    return in_dtype < o.in_dtype;
+}
+
+static int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+static TileCfg choose_tile(int Mblk)
+{
+    if (Mblk > 128) return {256, 64, 4, 1};
+    if (Mblk > 64) return {128, 64, 2, 2};
+    if (Mblk > 32) return {64, 64, 2, 2};
+    return {32, 128, 1, 4};
+}
+
+static int kt_of(int compute) { return compute == CMP_FP32 ? 16 : 32; }
+
+bool plan_build_host(const PlanKey &key, Plan *P, std::string *err)
+{
+    const int m = key.m;
+    if (m < 1 || m > kMaxOrder || key.n < 1 || key.p < 1 || key.bA < 1 || key.bC < 1) {
+        *err = "bad shape";
+        return false;
+    }
+    P->m = m;
+    P->n = key.n;
+    P->p = key.p;
+    P->bA = key.bA;
+    P->bC = key.bC;
+    P->prec = key.prec;
+    P->in_dtype = key.in_dtype;
+    const int64_t nbar64 = (key.n + key.bA - 1) / key.bA;
+    const int64_t pbar64 = (key.p + key.bC - 1) / key.bC;
+    if (nbar64 > (1 << 20) || pbar64 > (1 << 20)) {
+        *err = "too many blocks per mode";
+        return false;
+    }
+    const int nbar = (int)nbar64, pbar = (int)pbar64, bA = key.bA, bC = key.bC;
+    P->nbar = nbar;
+    P->pbar = pbar;
+    P->Kpad = (int64_t)nbar * bA;
+    P->Ppad = (int64_t)pbar * bC;
+    P->Kx = round_up(P->Kpad, 8);
+    if (P->Kpad > INT32_MAX / 2 || P->Ppad > INT32_MAX / 2) {
+        *err = "dimension too large";
+        return false;
+    }
+
+    // Compute form per level and storage type of each temporary.
+    int cmp[kMaxOrder], tdt[kMaxOrder];
+    for (int d = 0; d < m; ++d) {
+        switch (key.prec) {
+        case PREC_FP32: cmp[d] = CMP_FP32; break;
+        case PREC_BF16: cmp[d] = CMP_BF16; break;
+        case PREC_X3_FP32: cmp[d] = d == 0 ? CMP_X3 : CMP_FP32; break;
+        case PREC_X3_BF16: cmp[d] = d == 0 ? CMP_X3 : CMP_BF16; break;
+        default: *err = "bad precision"; return false;
+        }
+    }
+    for (int k = 1; k < m; ++k) {
+        const bool bf = key.prec == PREC_BF16 || key.prec == PREC_X3_BF16;
+        tdt[k] = bf ? BF16 : F32;
+    }
+
+    // Workspace: X panels first.
+    size_t ws = 0;
+    bool need[3] = {false, false, false};
+    for (int d = 0; d < m; ++d) {
+        if (cmp[d] == CMP_FP32) need[0] = true;
+        if (cmp[d] == CMP_BF16 || cmp[d] == CMP_X3) need[1] = true;
+        if (cmp[d] == CMP_X3) need[2] = true;
+    }
+    const size_t esz[3] = {4, 2, 2};
+    for (int s = 0; s < 3; ++s) {
+        if (!need[s]) continue;
+        P->xp_off[s] = (int64_t)ws;
+        ws += (size_t)round_up((int64_t)P->Ppad * P->Kx * esz[s], 256);
+    }
+    // Temporaries T^(m-1) .. T^(1).
+    for (int k = m - 1; k >= 1; --k) {
+        const int d = m - 1 - k;
+        const int64_t jt = binom(pbar + d, d + 1);
+        const int64_t pf = binom(nbar + k - 1, k);
+        int64_t blk = 1;
+        for (int j = 0; j < m; ++j) blk *= (j < k ? bA : bC);
+        if (jt < 0 || pf < 0 || blk <= 0) {
+            *err = "temporary too large";
+            return false;
+        }
+        const __int128 elems = (__int128)jt * pf * blk;
+        const __int128 bytes = elems * (tdt[k] == F32 ? 4 : 2);
+        if (bytes > ((__int128)1 << 46)) {
+            *err = "temporary too large";
+            return false;
+        }
+        P->temp_off[k] = (int64_t)ws;
+        P->temp_dtype[k] = tdt[k];
+        P->temp_jtuples[k] = jt;
+        P->temp_prefixes[k] = pf;
+        P->temp_block[k] = blk;
+        ws += (size_t)round_up((int64_t)bytes, 256);
+    }
+    P->ws_bytes = ws;
+
+    // Stages.
+    P->stages.clear();
+    P->flops = 0;
+    for (int d = 0; d < m; ++d) {
+        const int k = m - 1 - d;
+        StagePlan S;
+        S.d = d;
+        S.k = k;
+        S.compute = cmp[d];
+        const int in_dt = d == 0 ? key.in_dtype : tdt[k + 1];
+        const int out_dt = k == 0 ? F32 : tdt[k];
+        if (cmp[d] == CMP_FP32 && in_dt != F32) { *err = "fp32 contraction needs fp32 input"; return false; }
+        if (cmp[d] == CMP_X3 && in_dt != F32) { *err = "split contraction needs fp32 input"; return false; }
+
+        int ext_in[kMaxOrder], ext_out[kMaxOrder];
+        for (int j = 0; j < m; ++j) {
+            ext_in[j] = j <= k ? bA : bC;
+            ext_out[j] = j < k ? bA : bC;
+        }
+        int64_t gs[kMaxOrder], os[kMaxOrder];
+        int64_t in_blk = 1, out_blk = 1;
+        for (int j = 0; j < m; ++j) {
+            gs[j] = in_blk;
+            in_blk *= ext_in[j];
+            os[j] = out_blk;
+            out_blk *= ext_out[j];
+        }
+        if (in_blk > INT32_MAX / 2 || out_blk > INT32_MAX / 2) {
+            *err = "block too large";
+            return false;
+        }
+        const int Mblk = (int)(in_blk / ext_in[k]);
+
+        StageArgs &a = S.args;
+        a.m = m;
+        a.k = k;
+        a.nbar = nbar;
+        a.bA = bA;
+        a.bC = bC;
+        a.Kpad = (int32_t)P->Kpad;
+        a.Ppad = (int32_t)P->Ppad;
+        a.Kx = (int32_t)P->Kx;
+        a.Mblk = Mblk;
+        a.in_f32 = in_dt == F32;
+        a.out_f32 = out_dt == F32;
+        const int KT = kt_of(cmp[d]);
+        if (bA >= KT) {
+            a.chunk_blocks = 1;
+            a.chunk_k = KT;
+            a.chunks_per_blk = (bA + KT - 1) / KT;
+            a.nchunks = nbar * a.chunks_per_blk;
+        } else {
+            a.chunk_blocks = KT / bA;
+            a.chunk_k = bA;
+            a.chunks_per_blk = 1;
+            a.nchunks = (nbar + a.chunk_blocks - 1) / a.chunk_blocks;
+        }
+        int nm = 0;
+        for (int j = 0; j < m; ++j) {
+            if (j == k) continue;
+            a.mrad[nm] = ext_in[j];
+            a.mmode[nm] = j;
+            ++nm;
+        }
+        for (int i = nm; i < kMaxOrder; ++i) { a.mrad[i] = 1; a.mmode[i] = 0; }
+        for (int q = 0; q <= k; ++q) {
+            for (int j = 0; j < m; ++j) {
+                int pos;
+                if (j < k) pos = j < q ? j : j + 1;
+                else if (j == k) pos = q;
+                else pos = j;
+                a.sq[q][j] = (int32_t)gs[pos];
+            }
+        }
+        for (int j = 0; j < m; ++j) a.os[j] = (int32_t)os[j];
+        S.tile = choose_tile(Mblk);
+
+        // Row groups.
+        const std::vector<int32_t> Jp = sorted_tuples(d, pbar);
+        const int64_t nJp = d == 0 ? 1 : (int64_t)Jp.size() / d;
+        const std::vector<int32_t> Ss = sorted_tuples(k, nbar);
+        const int64_t nS = k == 0 ? 1 : (int64_t)Ss.size() / k;
+        const int64_t npre_out = k == 0 ? 1 : binom(nbar + k - 1, k);
+        const int64_t npre_in = binom(nbar + k, k + 1);
+        if ((int64_t)nJp * nS > INT32_MAX || (int64_t)nJp * nS * nbar > INT32_MAX) {
+            *err = "too many row groups";
+            return false;
+        }
+        S.groups.reserve(nJp * nS);
+        S.in_tab.reserve(nJp * nS * nbar);
+        int32_t u[kMaxOrder];
+        for (int64_t jp = 0; jp < nJp; ++jp) {
+            const int32_t *J = d ? &Jp[jp * d] : nullptr;
+            int64_t R = 0;   // colex rank of (jbar, J') minus jbar
+            for (int i = 1; i <= d; ++i) R += binom((int64_t)J[i - 1] + i, i + 1);
+            const int64_t rJ = d ? colex_rank(J, d) : 0;
+            const int jcount = d == 0 ? pbar : J[0] + 1;
+            for (int64_t si = 0; si < nS; ++si) {
+                const int32_t *s = k ? &Ss[si * k] : nullptr;
+                const int64_t rs = k ? colex_rank(s, k) : 0;
+                GroupDesc g;
+                g.out_base = (R * npre_out + rs) * out_blk;
+                g.out_jstride = npre_out * out_blk;
+                g.jcount = jcount;
+                g.in_row = (int32_t)S.in_tab.size();
+                S.groups.push_back(g);
+                for (int ib = 0; ib < nbar; ++ib) {
+                    int q = 0;
+                    while (q < k && s[q] <= ib) ++q;
+                    for (int i = 0; i < q; ++i) u[i] = s[i];
+                    u[q] = ib;
+                    for (int i = q; i < k; ++i) u[i + 1] = s[i];
+                    InEntry e;
+                    e.off = (rJ * npre_in + colex_rank(u, k + 1)) * in_blk;
+                    e.q = q;
+                    e.pad_ = 0;
+                    S.in_tab.push_back(e);
+                }
+                S.flops += 2 * P->Kpad * (int64_t)Mblk * jcount * bC;
+            }
+        }
+        // Tasks.
+        const int mtiles = (Mblk + S.tile.MT - 1) / S.tile.MT;
+        for (int32_t gi = 0; gi < (int32_t)S.groups.size(); ++gi) {
+            const int N = S.groups[gi].jcount * bC;
+            const int ntiles = (N + S.tile.NT - 1) / S.tile.NT;
+            for (int mt = 0; mt < mtiles; ++mt)
+                for (int nt = 0; nt < ntiles; ++nt) S.tasks.push_back(Task{gi, (int16_t)mt, (int16_t)nt});
+        }
+        if (mtiles > 32767 || S.tasks.size() > (size_t)INT32_MAX) {
+            *err = "too many tasks";
+            return false;
+        }
+        a.ntasks = (int32_t)S.tasks.size();
+        S.in_ws = d == 0 ? -1 : P->temp_off[k + 1];
+        S.out_ws = k == 0 ? -1 : P->temp_off[k];
+        S.out_elems = k == 0 ? 0 : P->temp_jtuples[k] * P->temp_prefixes[k] * P->temp_block[k];
+        if (cmp[d] == CMP_FP32) { S.xp_slot = 0; S.xp_lo_slot = -1; }
+        else if (cmp[d] == CMP_BF16) { S.xp_slot = 1; S.xp_lo_slot = -1; }
+        else { S.xp_slot = 1; S.xp_lo_slot = 2; }
+        P->flops += S.flops;
+        P->stages.push_back(std::move(S));
+    }
+    return true;
+}
+
+template <class T>
+static bool upload(const std::vector<T> &v, T **dst, std::string *err)
+{
+    *dst = nullptr;
+    if (v.empty()) return true;
+    if (hipMalloc((void **)dst, v.size() * sizeof(T)) != hipSuccess) {
+        *err = "hipMalloc failed for plan tables";
+        *dst = nullptr;
+        return false;
+    }
+    if (hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+        *err = "hipMemcpy failed for plan tables";
+        return false;
+    }
+    return true;
+}
+
+struct DevKey {
+    int dev;
+    PlanKey k;
+    bool operator<(const DevKey &o) const { return dev != o.dev ? dev < o.dev : k < o.k; }
+};
+
+static std::mutex g_plan_mu;
+static std::map<DevKey, std::unique_ptr<Plan>> g_plans;
+
+const Plan *plan_get(const PlanKey &key, std::string *err)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        *err = "hipGetDevice failed";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    DevKey dk{dev, key};
+    auto it = g_plans.find(dk);
+    if (it != g_plans.end()) return it->second.get();
+    std::unique_ptr<Plan> P(new Plan);
+    if (!plan_build_host(key, P.get(), err)) return nullptr;
+    for (auto &S : P->stages) {
+        if (!upload(S.groups, &S.d_groups, err) || !upload(S.in_tab, &S.d_in_tab, err) ||
+            !upload(S.tasks, &S.d_tasks, err))
+            return nullptr;   // tables of a failed plan are leaked, never used
+        S.args.groups = S.d_groups;
+        S.args.in_tab = S.d_in_tab;
+        S.args.tasks = S.d_tasks;
+    }
+    const Plan *out = P.get();
+    g_plans.emplace(dk, std::move(P));
+    return out;
+}
+
+// ------------------------------------------------------------------ meta table
+struct MetaKey {
+    int dev, m, nbar, b;
+    bool operator<(const MetaKey &o) const
+    {
+        if (dev != o.dev) return dev < o.dev;
+        if (m != o.m) return m < o.m;
+        if (nbar != o.nbar) return nbar < o.nbar;
+        return b < o.b;
+    }
+};
+static std::map<MetaKey, std::unique_ptr<MetaTable>> g_meta;
+
+const MetaTable *meta_get(int m, int nbar, int b, std::string *err)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        *err = "hipGetDevice failed";
+        return nullptr;
+    }
+    int64_t total = 1;
+    for (int j = 0; j < m; ++j) {
+        total *= nbar;
+        if (total > (1 << 24)) {
+            *err = "meta-data tensor too large (nbar^m > 2^24)";
+            return nullptr;
+        }
+    }
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    MetaKey key{dev, m, nbar, b};
+    auto it = g_meta.find(key);
+    if (it != g_meta.end()) return it->second.get();
+    std::unique_ptr<MetaTable> T(new MetaTable);
+    T->m = m;
+    T->nbar = nbar;
+    T->b = b;
+    T->tuples = sorted_tuples(m, nbar);
+    T->rank.resize(total);
+    T->perm.resize(total);
+    std::map<std::vector<int>, int> perm_ids;
+    int64_t bpow[kMaxOrder];
+    bpow[0] = 1;
+    for (int j = 1; j < m; ++j) bpow[j] = bpow[j - 1] * b;
+    int32_t t[kMaxOrder], u[kMaxOrder];
+    std::vector<int> sigma(m);
+    for (int64_t f = 0; f < total; ++f) {
+        int64_t r = f;
+        for (int j = 0; j < m; ++j) { t[j] = (int32_t)(r % nbar); r /= nbar; }
+        for (int j = 0; j < m; ++j) sigma[j] = j;
+        std::stable_sort(sigma.begin(), sigma.end(), [&](int x, int y) { return t[x] < t[y]; });
+        for (int j = 0; j < m; ++j) u[j] = t[sigma[j]];
+        T->rank[f] = colex_rank(u, m);
+        // logical mode sigma[i] sits at stored position i
+        std::vector<int> pos(m);
+        for (int i = 0; i < m; ++i) pos[sigma[i]] = i;
+        auto ins = perm_ids.emplace(pos, (int)perm_ids.size());
+        if (ins.second)
+            for (int j = 0; j < m; ++j) T->perm_strides.push_back((int32_t)bpow[pos[j]]);
+        T->perm[f] = ins.first->second;
+    }
+    if (!upload(T->rank, &T->d_rank, err) || !upload(T->perm, &T->d_perm, err) ||
+        !upload(T->perm_strides, &T->d_perm_strides, err) || !upload(T->tuples, &T->d_tuples, err))
+        return nullptr;
+    const MetaTable *out = T.get();
+    g_meta.emplace(key, std::move(T));
+    return out;
+}
+
+}  // namespace symt

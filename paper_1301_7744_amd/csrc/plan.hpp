@@ -1,0 +1,98 @@
+// Host-side plan for BCSS sttsm: block ranks, the meta-data tensor, per-stage
+// row groups, input-block tables and task lists, and the workspace layout.
+// Built once per shape and precision, uploaded to the device once, cached.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace symt {
+
+// binom(n, k) exactly; -1 on overflow or n < 0.
+int64_t binom(int64_t n, int64_t k);
+// Colex rank of a sorted tuple: sum_i binom(s_i + i, i + 1).
+int64_t colex_rank(const int32_t *s, int len);
+// All sorted len-tuples over [0, N) in colex order, flattened (len ints each).
+std::vector<int32_t> sorted_tuples(int len, int N);
+
+// Tile shape of one stage launch.
+struct TileCfg {
+    int MT, NT, WM, WN;
+};
+
+struct StagePlan {
+    int d = 0;          // loop level (0 forms T^(m-1))
+    int k = 0;          // contracted mode
+    int compute = CMP_FP32;
+    TileCfg tile{};
+    StageArgs args{};   // everything but in/out/xp pointers
+    std::vector<GroupDesc> groups;
+    std::vector<InEntry> in_tab;
+    std::vector<Task> tasks;
+    // Device copies (owned by the plan).
+    GroupDesc *d_groups = nullptr;
+    InEntry *d_in_tab = nullptr;
+    Task *d_tasks = nullptr;
+    // Where the operands live: -1 means the caller's A (input) or C (output),
+    // otherwise a byte offset into the workspace.
+    int64_t in_ws = -1, out_ws = -1;
+    int xp_slot = 0, xp_lo_slot = -1;  // which padded-X panel (see Plan::xp_off)
+    int64_t flops = 0;
+    int64_t out_elems = 0;
+};
+
+struct Plan {
+    int m = 0;
+    int64_t n = 0, p = 0;
+    int bA = 0, bC = 0;
+    int nbar = 0, pbar = 0;
+    int prec = 0, in_dtype = 0;
+    int64_t Kpad = 0, Ppad = 0, Kx = 0;   // Kx: row stride of the X panels
+    // X panels in the workspace: slot 0 fp32, slot 1 bf16 (rounded), slot 2 bf16 lo.
+    int64_t xp_off[3] = {-1, -1, -1};
+    // Temporaries T^(k), k = 1..m-1.
+    int64_t temp_off[kMaxOrder] = {};
+    int temp_dtype[kMaxOrder] = {};
+    int64_t temp_jtuples[kMaxOrder] = {};
+    int64_t temp_prefixes[kMaxOrder] = {};
+    int64_t temp_block[kMaxOrder] = {};
+    size_t ws_bytes = 0;
+    int64_t flops = 0;
+    std::vector<StagePlan> stages;
+};
+
+struct PlanKey {
+    int m;
+    int64_t n, p;
+    int bA, bC, prec, in_dtype;
+    bool operator<(const PlanKey &o) const;
+};
+
+// Builds (first call) or returns the cached plan; uploads device tables.
+// Returns nullptr and fills *err on failure.
+const Plan *plan_get(const PlanKey &key, std::string *err);
+// Host part only (no device upload); for size queries.  Caller owns result.
+bool plan_build_host(const PlanKey &key, Plan *out, std::string *err);
+
+// Meta-data tensor of App. B for an order-m BCSS with nbar blocks per mode:
+// for every block t (dimensional order over nbar^m) the rank of sort(t) and a
+// permutation id; perm_strides[id*m + j] is the stride, inside the stored
+// block of extent b, of logical mode j.
+struct MetaTable {
+    int m = 0, nbar = 0, b = 0;
+    std::vector<int64_t> rank;       // nbar^m
+    std::vector<int32_t> perm;       // nbar^m
+    std::vector<int32_t> perm_strides;
+    std::vector<int32_t> tuples;     // sorted block tuples in colex order, m each
+    int64_t *d_rank = nullptr;
+    int32_t *d_perm = nullptr;
+    int32_t *d_perm_strides = nullptr;
+    int32_t *d_tuples = nullptr;
+};
+const MetaTable *meta_get(int m, int nbar, int b, std::string *err);
+
+}  // namespace symt

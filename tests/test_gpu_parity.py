@@ -1,0 +1,314 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Integer/byte work (pack, unpack, padding) is compared bit for bit; floating
+point results by relative Frobenius error over the dense C with the bounds in
+gpu_util (FP32 1e-5; BF16 sqrt(2m) 2^-8; split-BF16x3 2e-5)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import bcss_ref, closed_forms
+import synth
+from gpu_util import (TOL_FP32, TOL_X3_FIRST_FP32, TOL_X3_STAGE0, dev_dense, err, padding_mask, ref_bcss,
+                      run, say, tol_bf16)
+
+pytestmark = pytest.mark.gpu
+
+P32, PBF, PX3F, PX3B = 0, 1, 2, 3
+
+
+def st():
+    import paper_1301_7744_amd
+    return paper_1301_7744_amd
+
+
+# ------------------------------------------------------------------ pack / unpack
+PACK_CASES = [(1, 5, 2), (2, 7, 3), (3, 16, 4), (3, 10, 4), (4, 9, 2), (5, 6, 2), (6, 5, 2), (3, 3, 4),
+              (2, 130, 16), (3, 256, 16), (8, 2, 1)]
+
+
+@pytest.mark.parametrize("m,n,b", PACK_CASES)
+def test_pack_bitexact(m, n, b):
+    import torch
+    say("pack", m, n, b)
+    A = synth.symmetric_uniform(m, n, (m, n, b, 1))
+    got = st().bcss_pack(dev_dense(A), m, n, b)
+    torch.cuda.synchronize()
+    ref = bcss_ref.pack(A, b)
+    assert np.array_equal(got.cpu().numpy().reshape(ref.shape), ref)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f64"])
+def test_pack_unpack_other_dtypes(dt):
+    import torch
+    tdt = {"bf16": torch.bfloat16, "f64": torch.float64}[dt]
+    m, n, b = 3, 11, 4
+    A = synth.symmetric_uniform(m, n, 5)
+    if dt == "bf16":
+        A = synth.round_to_bf16(A)
+    Ad = dev_dense(A.astype(np.float64 if dt == "f64" else np.float32), tdt)
+    P = st().bcss_pack(Ad, m, n, b)
+    D = st().bcss_unpack(P, m, n, b)
+    torch.cuda.synchronize()
+    assert torch.equal(D, Ad)
+    ref = bcss_ref.pack(A, b)
+    assert np.array_equal(P.to(torch.float64).cpu().numpy().reshape(ref.shape), ref)
+
+
+@pytest.mark.parametrize("m,n,b", PACK_CASES)
+def test_unpack_bitexact(m, n, b):
+    """unpack(pack(A)) == A, and unpack of an arbitrary (non-symmetric) BCSS
+    array equals the oracle's unpack, which shows the permuted reads."""
+    import torch
+    say("unpack", m, n, b)
+    A = synth.symmetric_uniform(m, n, (m, n, b, 2))
+    Ad = dev_dense(A)
+    D = st().bcss_unpack(st().bcss_pack(Ad, m, n, b), m, n, b)
+    torch.cuda.synchronize()
+    assert torch.equal(D, Ad)
+    if n ** m <= 300_000:
+        nb = st().bcss_num_blocks(m, -(-n // b))
+        B = synth.rng((m, n, b, 3)).standard_normal((nb, b ** m)).astype(np.float32)
+        Dd = st().bcss_unpack(torch.from_numpy(B.ravel()).cuda(), m, n, b)
+        torch.cuda.synchronize()
+        ref = bcss_ref.unpack(B, m, n, b)
+        assert np.array_equal(Dd.cpu().numpy(), ref.ravel(order="F"))
+
+
+# ------------------------------------------------------------------ FP32 sttsm
+SMALL = [(m, n, p, bA, bC) for m, n, p, bA, bC in [
+    (1, 5, 3, 2, 2), (1, 40, 33, 16, 8),
+    (2, 5, 3, 2, 1), (2, 7, 7, 3, 3), (2, 17, 9, 4, 8), (2, 33, 40, 16, 16), (2, 70, 65, 64, 64),
+    (3, 5, 5, 2, 2), (3, 6, 4, 3, 2), (3, 9, 11, 4, 4), (3, 16, 16, 4, 4), (3, 20, 13, 8, 4), (3, 35, 35, 16, 16),
+    (4, 5, 4, 2, 3), (4, 9, 9, 4, 4), (4, 12, 7, 4, 2), (4, 17, 10, 8, 4),
+    (5, 4, 5, 2, 2), (5, 7, 6, 4, 3),
+    (6, 4, 4, 2, 2), (6, 5, 3, 2, 1),
+    (7, 3, 3, 1, 2), (8, 2, 2, 1, 1), (3, 3, 2, 4, 4), (3, 1, 1, 1, 1),
+]]
+
+
+@pytest.mark.parametrize("m,n,p,bA,bC", SMALL)
+def test_fp32_small_vs_oracle(m, n, p, bA, bC):
+    """Several tiles and ragged tails, p != n, bA != bC, n < b, m = 1..8."""
+    say("fp32", m, n, p, bA, bC)
+    A = synth.symmetric_uniform(m, n, (m, n, p, 11))
+    X = synth.change_of_basis(p, n, (m, n, p, 12))
+    got = run(A, X, bA, bC, P32)
+    ref = ref_bcss(A.astype(np.float64), X.astype(np.float64), bC)
+    e = err(got, ref, m, p, bC)
+    say("  rel err", e)
+    assert e <= TOL_FP32
+    mask = padding_mask(m, p, bC)
+    assert np.all(got[mask] == 0.0)
+
+
+def test_fp32_config1_vs_direct_sum():
+    """m=3, n=p=16, b=4 against the literal direct sum (O1)."""
+    A, X = synth.make_config_inputs("m3_n16_b4")
+    got = run(A, X, 4, 4, P32)
+    ref = ref_bcss(A.astype(np.float64), X.astype(np.float64), 4, method="direct")
+    e = err(got, ref, 3, 16, 4)
+    say("config1 fp32 rel err", e)
+    assert e <= TOL_FP32
+
+
+def test_fp32_config2_full():
+    """m=3, n=p=256, b=16 (the measured workload): full C against O2 and
+    64 sampled entries against the literal per-entry sum (O3)."""
+    A, X = synth.make_config_inputs("m3_n256_b16")
+    got = run(A, X, 16, 16, P32)
+    A64, X64 = A.astype(np.float64), X.astype(np.float64)
+    Cd = oracle.chain(A64, X64)
+    e = err(got, bcss_ref.pack(Cd, 16), 3, 256, 16)
+    say("config2 fp32 rel err", e)
+    assert e <= TOL_FP32
+    index = bcss_ref.block_index(3, 16)
+    g = synth.rng(7)
+    scale = np.abs(Cd).max()
+    for _ in range(64):
+        j = np.sort(g.integers(0, 256, size=3))[g.permutation(3)]
+        lit = oracle.entry(A64, X64, j)
+        u = sorted(range(3), key=lambda i: j[i] // 16)
+        blk = tuple(int(j[i] // 16) for i in u)
+        loc = [int(j[i] % 16) for i in u]
+        gpu = got[index[blk], loc[0] + 16 * loc[1] + 256 * loc[2]]
+        assert abs(gpu - lit) <= 1e-5 * scale
+
+
+def test_temporaries_match_oracle():
+    """Every stored block of every GPU temporary T^(k) equals O2's dense T^(k)
+    restricted to that block (FP32 tolerance per block set)."""
+    import torch
+    for (m, n, p, bA, bC) in [(3, 16, 16, 4, 4), (4, 9, 7, 4, 3), (3, 35, 20, 16, 8)]:
+        say("temps", m, n, p, bA, bC)
+        A = synth.symmetric_uniform(m, n, (m, n, 21))
+        X = synth.change_of_basis(p, n, (m, n, 22))
+        _, ws = run(A, X, bA, bC, P32, keep_ws=True)
+        _, temps = oracle.chain(A.astype(np.float64), X.astype(np.float64), keep_temps=True)
+        nbar, pbar = -(-n // bA), -(-p // bC)
+        for k in range(1, m):
+            T = st().temporary(ws, m, n, p, bA, bC, P32, k).double().cpu().numpy()
+            dense = temps[k]
+            pad = np.zeros((nbar * bA,) * k + (pbar * bC,) * (m - k))
+            pad[tuple(slice(0, n) for _ in range(k)) + tuple(slice(0, p) for _ in range(m - k))] = dense
+            jt = bcss_ref.sorted_block_tuples(m - k, pbar)
+            pf = bcss_ref.sorted_block_tuples(k, nbar) if k else [()]
+            shape = (bA,) * k + (bC,) * (m - k)
+            num = den = 0.0
+            for r, J in enumerate(jt):
+                for q, s in enumerate(pf):
+                    sl = tuple(slice(si * bA, (si + 1) * bA) for si in s) + \
+                        tuple(slice(ji * bC, (ji + 1) * bC) for ji in J)
+                    ref = pad[sl].ravel(order="F")
+                    num += float(np.sum((T[r, q] - ref) ** 2))
+                    den += float(np.sum(ref ** 2))
+            e = (num / den) ** 0.5
+            say("  T^(%d) rel err" % k, e)
+            assert e <= TOL_FP32
+        del ws
+        torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------------ reduced precision
+@pytest.mark.parametrize("prec", [PBF, PX3F, PX3B])
+@pytest.mark.parametrize("case", [(3, 16, 16, 4, 4), (3, 35, 20, 16, 8), (4, 17, 10, 8, 4), (2, 70, 65, 64, 64),
+                                  (5, 7, 6, 4, 3)])
+def test_reduced_precision_small(prec, case):
+    m, n, p, bA, bC = case
+    say("prec", prec, case)
+    A = synth.symmetric_uniform(m, n, (m, n, 31))
+    X = synth.change_of_basis(p, n, (m, n, 32))
+    got = run(A, X, bA, bC, prec)
+    ref = ref_bcss(A.astype(np.float64), X.astype(np.float64), bC)
+    e = err(got, ref, m, p, bC)
+    bound = {PBF: tol_bf16(m), PX3F: TOL_X3_FIRST_FP32, PX3B: tol_bf16(m)}[prec]
+    say("  rel err", e, "bound", bound)
+    assert e <= bound
+    assert np.all(got[padding_mask(m, p, bC)] == 0.0)
+
+
+def test_bf16_inputs():
+    """BF16 A and X (the served precision): the oracle gets the same bf16 values."""
+    import torch
+    m, n, p, b = 3, 40, 24, 8
+    A = synth.round_to_bf16(synth.symmetric_uniform(m, n, 41))
+    X = synth.round_to_bf16(synth.change_of_basis(p, n, 42))
+    got = run(A, X, b, b, PBF, dtype=torch.bfloat16)
+    e = err(got, ref_bcss(A.astype(np.float64), X.astype(np.float64), b), m, p, b)
+    say("bf16-input rel err", e)
+    assert e <= tol_bf16(m)
+
+
+def test_split_stage0_recovers_fp32():
+    """split-BF16x3: the first temporary T^(m-1) alone is within 1e-5 of O2,
+    while plain BF16 is not."""
+    m, n, p, b = 3, 64, 64, 16
+    A = synth.symmetric_uniform(m, n, 51)
+    X = synth.change_of_basis(p, n, 52)
+    _, temps = oracle.chain(A.astype(np.float64), X.astype(np.float64), keep_temps=True)
+    ref = temps[m - 1]
+    errs = {}
+    for prec in (PX3F, PBF):
+        _, ws = run(A, X, b, b, prec, keep_ws=True)
+        T = st().temporary(ws, m, n, p, b, b, prec, m - 1).double().cpu().numpy()
+        nbar = n // b
+        pf = bcss_ref.sorted_block_tuples(m - 1, nbar)
+        num = den = 0.0
+        for jb in range(p // b):
+            for q, s in enumerate(pf):
+                sl = tuple(slice(si * b, (si + 1) * b) for si in s) + (slice(jb * b, (jb + 1) * b),)
+                r = ref[sl].ravel(order="F")
+                num += float(np.sum((T[jb, q] - r) ** 2))
+                den += float(np.sum(r ** 2))
+        errs[prec] = (num / den) ** 0.5
+    say("T^(m-1) errors", errs)
+    assert errs[PX3F] <= TOL_X3_STAGE0
+    assert errs[PBF] > 10 * errs[PX3F]
+
+
+# ------------------------------------------------------------------ full-size sweep
+SWEEP = ["m2_n4096_b64", "m4_n64_b8", "m5_n32_b4", "m6_n24_b4"]
+
+
+@pytest.fixture(scope="module")
+def sweep_refs():
+    return {}
+
+
+@pytest.mark.parametrize("prec", [P32, PBF, PX3F])
+@pytest.mark.parametrize("name", SWEEP)
+def test_order_sweep_full(name, prec, sweep_refs):
+    c = synth.CONFIGS[name]
+    m, n, p, b = c["m"], c["n"], c["p"], c["bA"]
+    say("sweep", name, prec)
+    A, X = synth.make_config_inputs(name)
+    if name not in sweep_refs:
+        A64, X64 = A.astype(np.float64), X.astype(np.float64)
+        Cd = closed_forms.matrix_case(A64, X64) if m == 2 else oracle.chain(A64, X64)
+        sweep_refs[name] = bcss_ref.pack(np.asfortranarray(Cd), b)
+    got = run(A, X, b, b, prec)
+    e = err(got, sweep_refs[name], m, p, b)
+    bound = {P32: TOL_FP32, PBF: tol_bf16(m), PX3F: TOL_X3_FIRST_FP32}[prec]
+    say("  rel err", e, "bound", bound)
+    assert e <= bound
+
+
+@pytest.mark.parametrize("prec", [P32, PBF])
+@pytest.mark.parametrize("case", synth.rect_cases(), ids=lambda c: c["name"])
+def test_rank8_rectangular(case, prec):
+    """m=4, p=32, rank-8 A: against the closed form sum lam (X a)^{o4}."""
+    m, n, p, bA, bC = case["m"], case["n"], case["p"], case["bA"], case["bC"]
+    say("rect", case["name"], prec)
+    lams, vecs = synth.rank_r_factors(n, case["rank"], case["seed"])
+    A64 = synth.rank_r_symmetric(m, lams, vecs)
+    X = synth.change_of_basis(p, n, case["seed"] + 1000)
+    A = A64.astype(np.float32)
+    got = run(A, X, bA, bC, prec)
+    # the GPU sees A rounded to fp32: compare with the exact result for those values
+    ref = bcss_ref.pack(oracle.chain(A.astype(np.float64), X.astype(np.float64)), bC)
+    e = err(got, ref, m, p, bC)
+    closed = bcss_ref.pack(closed_forms.rank_r(lams, vecs, X.astype(np.float64), m), bC)
+    e_closed = err(got, closed, m, p, bC)
+    bound = TOL_FP32 if prec == P32 else tol_bf16(m)
+    say("  rel err", e, "vs closed form", e_closed)
+    assert e <= bound and e_closed <= bound
+    assert np.all(got[padding_mask(m, p, bC)] == 0.0)
+
+
+# ------------------------------------------------------------------ edge cases
+def test_zero_inputs_give_exact_zero():
+    m, n, p, b = 3, 20, 18, 8
+    A = synth.symmetric_uniform(m, n, 61)
+    assert np.all(run(A, np.zeros((p, n), np.float32), b, b, P32) == 0.0)
+    assert np.all(run(np.zeros_like(A), synth.change_of_basis(p, n, 62), b, b, PBF) == 0.0)
+
+
+def test_deterministic_reruns():
+    m, n, p, b = 3, 48, 48, 16
+    A = synth.symmetric_uniform(m, n, 71)
+    X = synth.change_of_basis(p, n, 72)
+    for prec in (P32, PBF, PX3F):
+        assert np.array_equal(run(A, X, b, b, prec), run(A, X, b, b, prec))
+
+
+def test_workspace_too_small_rejected():
+    """Through the raw C ABI: a workspace one byte short returns EINVAL."""
+    import ctypes
+    import torch
+    lib = st().load()
+    m, n, p, b = 3, 16, 16, 4
+    A = synth.symmetric_uniform(m, n, 81)
+    Ab = st().bcss_pack(dev_dense(A), m, n, b)
+    X = torch.zeros(p, n, device="cuda")
+    C = torch.empty(st().bcss_num_elems(m, p, b), device="cuda")
+    need = st().sttsm_workspace_bytes(m, n, p, b, b)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    LA, LC = st().layout(m, n, b), st().layout(m, p, b)
+    rc = lib.sttsm(ctypes.byref(LA), Ab.data_ptr(), X.data_ptr(), n, 1, ctypes.byref(LC), C.data_ptr(), P32,
+                   ws.data_ptr(), need - 1, None)
+    assert rc == -1 and b"workspace" in lib.sttsm_last_error()
+    rc = lib.sttsm(ctypes.byref(LA), Ab.data_ptr(), X.data_ptr(), n, 1, ctypes.byref(LC), C.data_ptr(), P32,
+                   ws.data_ptr(), need, None)
+    torch.cuda.synchronize()
+    assert rc == 0
