@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -93,6 +94,8 @@ int make_key(const bcss_layout *A, const bcss_layout *C, int32_t prec, PlanKey *
     key->bC = C->b;
     key->prec = prec;
     key->in_dtype = A->dtype == STTSM_F32 ? F32 : BF16;
+    const char *gen = getenv("STTSM_GENERIC_KERNELS");
+    key->generic_only = gen && gen[0] == '1';
     return STTSM_OK;
 }
 
@@ -239,9 +242,13 @@ int sttsm(const bcss_layout *A, const void *A_dev, const void *X_dev, int64_t rs
     float *x32 = P->xp_off[0] >= 0 ? (float *)(w + P->xp_off[0]) : nullptr;
     uint16_t *xhi = P->xp_off[1] >= 0 ? (uint16_t *)(w + P->xp_off[1]) : nullptr;
     uint16_t *xlo = P->xp_off[2] >= 0 ? (uint16_t *)(w + P->xp_off[2]) : nullptr;
-    if (launch_prep_x(dtype_size(A->dtype), X_dev, rs_x, cs_x, P->p, P->n, P->Ppad, P->Kx, x32, xhi, xlo, s))
+    if ((x32 || xhi || xlo) &&
+        launch_prep_x(dtype_size(A->dtype), X_dev, rs_x, cs_x, P->p, P->n, P->Ppad, P->Kx, x32, xhi, xlo, s))
         return fail(STTSM_EHIP, std::string("X panel launch failed: ") + hipGetErrorString(hipGetLastError()));
-    const void *slot_ptr[3] = {x32, xhi, xlo};
+    float *xt = P->xp_off[3] >= 0 ? (float *)(w + P->xp_off[3]) : nullptr;
+    if (xt && launch_prep_xt(dtype_size(A->dtype), X_dev, rs_x, cs_x, P->p, P->n, P->Kt, P->Pt, xt, s))
+        return fail(STTSM_EHIP, std::string("X panel launch failed: ") + hipGetErrorString(hipGetLastError()));
+    const void *slot_ptr[4] = {x32, xhi, xlo, xt};
     for (const StagePlan &S : P->stages) {
         StageArgs a = S.args;
         a.in = S.in_ws < 0 ? A_dev : (const void *)(w + S.in_ws);
@@ -250,7 +257,8 @@ int sttsm(const bcss_layout *A, const void *A_dev, const void *X_dev, int64_t rs
         a.xp_lo = S.xp_lo_slot >= 0 ? slot_ptr[S.xp_lo_slot] : nullptr;
         const long slot = prof_slot(S.d);
         if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot], s);
-        if (launch_stage(a, S.compute, S.tile.MT, S.d == 0, s))
+        const int lrc = S.fast ? launch_stage_fast(a, S.tile.MT, S.tile.NT, S.tile.KT, S.tile.PD, S.d == 0, s) : launch_stage(a, S.compute, S.tile.MT, S.d == 0, s);
+        if (lrc)
             return fail(STTSM_EHIP, std::string("stage launch failed: ") + hipGetErrorString(hipGetLastError()));
         if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot + 1], s);
     }

@@ -76,6 +76,21 @@ struct StageArgs {
     int32_t sq[kMaxOrder][kMaxOrder];
     // Strides of the output block (dimensional order).
     int32_t os[kMaxOrder];
+    // Block-copy staging (stage_fast kernels): extents and strides of the
+    // stored input block, and for insertion position q the LDS stride of the
+    // logical mode found at stored position i: lds[q][i].
+    int32_t ext_in[kMaxOrder];
+    int32_t gs[kMaxOrder];
+    int32_t lds[kMaxOrder][kMaxOrder];
+    int32_t xt_stride;       // row stride of the transposed X panel [Kt][xt_stride]
+    int32_t mos[kMaxOrder];  // os[mmode[i]]: output stride of the i-th M digit
+    int32_t osk;             // os[k]: output stride of the contracted (now C-block) mode
+    // Block-copy kernel tables (per launch): stored digits of each thread's
+    // float4, fdig[((mt*NF + f)*m + i)*256 + t], and output offset of each
+    // block row, fopart[row].
+    const int32_t *fdig;
+    const int32_t *fopart;
 };
+
 
 }  // namespace symt

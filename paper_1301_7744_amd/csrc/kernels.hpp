@@ -15,5 +15,11 @@ int launch_unpack(int esize, const void *bcss, void *dense, int m, int64_t n, in
 int launch_prep_x(int esize, const void *X, int64_t rs, int64_t cs, int64_t p, int64_t n, int64_t Ppad,
                   int64_t Kx, float *x32, uint16_t *xhi, uint16_t *xlo, hipStream_t s);
 int launch_stage(const StageArgs &a, int compute, int MT, bool first, hipStream_t s);
+int launch_stage_fast(const StageArgs &a, int MT, int NT, int KT, int PD, bool first, hipStream_t s);
+bool fast_tile_supported(int MT, int NT, int KT, int PD);
+// Whether the block-copy kernel is instantiated for order m and nbar blocks.
+bool fast_supported(int m, int nbar);
+int launch_prep_xt(int esize, const void *X, int64_t rs, int64_t cs, int64_t p, int64_t n, int64_t Kt, int64_t Pt,
+                   float *xt, hipStream_t s);
 
 }  // namespace symt

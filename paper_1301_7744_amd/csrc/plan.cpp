@@ -1,9 +1,13 @@
 // Host plan for BCSS sttsm (see plan.hpp).
 #include "plan.hpp"
 
+#include "kernels.hpp"
+
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -55,7 +59,8 @@ bool PlanKey::operator<(const PlanKey &o) const
     if (bA != o.bA) return bA < o.bA;
     if (bC != o.bC) return bC < o.bC;
     if (prec != o.prec) return prec < o.prec;
-    return in_dtype < o.in_dtype;
+    if (in_dtype != o.in_dtype) return in_dtype < o.in_dtype;
+    return generic_only < o.generic_only;
 }
 
 static int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -66,6 +71,58 @@ static TileCfg choose_tile(int Mblk)
     if (Mblk > 64) return {128, 64, 2, 2};
     if (Mblk > 32) return {64, 64, 2, 2};
     return {32, 128, 1, 4};
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup i on XCD
+// i mod 8), each with its own L2.  Deal whole row groups to XCDs so that all
+// tiles of a group, which read the same input blocks, run on one XCD close
+// together in time: list position 8*l + x holds the l-th task of XCD x.
+static void order_tasks_for_xcds(std::vector<Task> *tasks)
+{
+    constexpr int kXcd = 8;
+    std::vector<std::vector<Task>> bins(kXcd);
+    size_t i = 0, gi = 0;
+    std::vector<size_t> load(kXcd, 0);
+    while (i < tasks->size()) {
+        size_t j = i;
+        while (j < tasks->size() && (*tasks)[j].group == (*tasks)[i].group) ++j;
+        // least-loaded XCD takes the next group (ties: round robin)
+        int best = (int)(gi % kXcd);
+        for (int x = 0; x < kXcd; ++x)
+            if (load[x] < load[best]) best = x;
+        for (size_t t = i; t < j; ++t) bins[best].push_back((*tasks)[t]);
+        load[best] += j - i;
+        ++gi;
+        i = j;
+    }
+    std::vector<Task> out;
+    out.reserve(tasks->size());
+    size_t longest = 0;
+    for (auto &b : bins) longest = std::max(longest, b.size());
+    for (size_t l = 0; l < longest; ++l)
+        for (int x = 0; x < kXcd; ++x)
+            if (l < bins[x].size()) out.push_back(bins[x][l]);
+    tasks->swap(out);
+}
+
+// Tile override for tuning experiments: STTSM_FAST_TILE="MTxNTxKTxPD" for
+// every level, or a comma-separated list per level (missing levels keep the
+// default).
+static bool fast_tile_override(int level, int *mt, int *nt, int *kt, int *pd)
+{
+    const char *e = getenv("STTSM_FAST_TILE");
+    if (!e || !*e) return false;
+    std::string str(e);
+    std::vector<std::string> parts;
+    size_t pos = 0;
+    while (pos <= str.size()) {
+        size_t c = str.find(',', pos);
+        if (c == std::string::npos) c = str.size();
+        parts.push_back(str.substr(pos, c - pos));
+        pos = c + 1;
+    }
+    const std::string &p = parts.size() == 1 ? parts[0] : (level < (int)parts.size() ? parts[level] : std::string());
+    return sscanf(p.c_str(), "%dx%dx%dx%d", mt, nt, kt, pd) == 4;
 }
 
 static int kt_of(int compute) { return compute == CMP_FP32 ? 16 : 32; }
@@ -96,6 +153,8 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err)
     P->Kpad = (int64_t)nbar * bA;
     P->Ppad = (int64_t)pbar * bC;
     P->Kx = round_up(P->Kpad, 8);
+    P->Kt = round_up(P->Kpad, 32);
+    P->Pt = round_up(P->Ppad, 128);
     if (P->Kpad > INT32_MAX / 2 || P->Ppad > INT32_MAX / 2) {
         *err = "dimension too large";
         return false;
@@ -117,19 +176,35 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err)
         tdt[k] = bf ? BF16 : F32;
     }
 
+    // Which levels take the block-copy kernel: fp32 operands, input blocks
+    // whose entries without the contracted mode number exactly 256, and bA
+    // dividing the 16-wide K chunk with at least 4 (one float4 per row run).
+    bool fast[kMaxOrder];
+    for (int d = 0; d < m; ++d) {
+        const int k = m - 1 - d;
+        int64_t mblk = 1;
+        for (int j = 0; j < m; ++j)
+            if (j != k) mblk *= (j <= k ? bA : bC);
+        const int in_dt = d == 0 ? key.in_dtype : tdt[k + 1];
+        fast[d] = cmp[d] == CMP_FP32 && in_dt == F32 && mblk == 256 && (bA == 4 || bA == 8 || bA == 16) &&
+                  bC % 4 == 0 && !key.generic_only && fast_supported(m, nbar);
+    }
+
     // Workspace: X panels first.
     size_t ws = 0;
-    bool need[3] = {false, false, false};
+    bool need[4] = {false, false, false, false};
     for (int d = 0; d < m; ++d) {
-        if (cmp[d] == CMP_FP32) need[0] = true;
+        if (cmp[d] == CMP_FP32 && !fast[d]) need[0] = true;
+        if (cmp[d] == CMP_FP32 && fast[d]) need[3] = true;
         if (cmp[d] == CMP_BF16 || cmp[d] == CMP_X3) need[1] = true;
         if (cmp[d] == CMP_X3) need[2] = true;
     }
     const size_t esz[3] = {4, 2, 2};
-    for (int s = 0; s < 3; ++s) {
+    for (int s = 0; s < 4; ++s) {
         if (!need[s]) continue;
         P->xp_off[s] = (int64_t)ws;
-        ws += (size_t)round_up((int64_t)P->Ppad * P->Kx * esz[s], 256);
+        const int64_t bytes = s < 3 ? (int64_t)P->Ppad * P->Kx * (int64_t)esz[s] : P->Kt * P->Pt * 4;
+        ws += (size_t)round_up(bytes, 256);
     }
     // Temporaries T^(m-1) .. T^(1).
     for (int k = m - 1; k >= 1; --k) {
@@ -232,8 +307,15 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err)
             }
         }
         for (int j = 0; j < m; ++j) a.os[j] = (int32_t)os[j];
+        for (int i = 0; i < kMaxOrder; ++i) a.mos[i] = i < m - 1 ? (int32_t)os[a.mmode[i]] : 0;
+        a.osk = (int32_t)os[k];
         S.tile = choose_tile(Mblk);
-
+        S.fast = fast[d];
+        for (int j = 0; j < m; ++j) {
+            a.ext_in[j] = ext_in[j];
+            a.gs[j] = (int32_t)gs[j];
+        }
+        a.xt_stride = (int32_t)P->Pt;
         // Row groups.
         const std::vector<int32_t> Jp = sorted_tuples(d, pbar);
         const int64_t nJp = d == 0 ? 1 : (int64_t)Jp.size() / d;
@@ -278,6 +360,71 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err)
                 S.flops += 2 * P->Kpad * (int64_t)Mblk * jcount * bC;
             }
         }
+        if (S.fast) {
+            // Tile of the block-copy kernel.  Below the first level a tile may
+            // take half a block row (split along mode m-1, contiguous in
+            // storage) when a half block still holds >= 256 float4.
+            const bool can_half = k < m - 1 && bC % 2 == 0 && bA >= 8;
+            int64_t t64 = 0;
+            for (const GroupDesc &gd : S.groups) t64 += (gd.jcount * bC + 63) / 64;
+            // Measured on m=3, n=p=256, b=16: a whole block row with 64
+            // columns for the first level, half rows with 128 columns for
+            // middle levels and 64 for the last.
+            S.tile = TileCfg{256, 64, 4, 1, 16, 1};
+            if (can_half) S.tile = k == 0 ? TileCfg{128, 64, 2, 2, 16, 1} : TileCfg{128, 128, 2, 2, 16, 1};
+            (void)t64;
+            int tmt, tnt, tkt, tpd;
+            if (fast_tile_override(d, &tmt, &tnt, &tkt, &tpd) && fast_tile_supported(tmt, tnt, tkt, tpd) &&
+                (tmt == 256 || can_half) && tkt % bA == 0)
+                S.tile = TileCfg{tmt, tnt, tmt / 64, 4 / (tmt / 64), tkt, tpd};
+            a.chunk_blocks = S.tile.KT / bA;
+            a.chunk_k = bA;
+            a.chunks_per_blk = 1;
+            a.nchunks = (nbar + a.chunk_blocks - 1) / a.chunk_blocks;
+            const int RS = S.tile.MT + 4;
+            int64_t ms[kMaxOrder] = {};
+            int64_t pv = 1;
+            for (int j = 0; j < m; ++j) {
+                if (j == k) continue;
+                ms[j] = pv;
+                pv *= ext_in[j];
+            }
+            for (int q = 0; q < kMaxOrder; ++q)
+                for (int i = 0; i < kMaxOrder; ++i) a.lds[q][i] = 0;
+            for (int q = 0; q <= k; ++q)
+                for (int i = 0; i < m; ++i) {
+                    int j;   // logical mode at stored position i
+                    if (i < q) j = i;
+                    else if (i == q) j = k;
+                    else if (i <= k) j = i - 1;
+                    else j = i;
+                    a.lds[q][i] = j == k ? RS : (int32_t)ms[j];
+                }
+            // Per-thread stored digits of the float4 each thread copies.
+            const int MT = S.tile.MT, NF = MT * S.tile.KT / 1024, sub4 = MT * bA / 4;
+            const int mt_count = Mblk / MT;
+            S.fdig.assign((size_t)mt_count * NF * m * 256, 0);
+            for (int mt = 0; mt < mt_count; ++mt)
+                for (int f = 0; f < NF; ++f)
+                    for (int t = 0; t < 256; ++t) {
+                        const int F = t + 256 * f, gq = (256 * f) / sub4;
+                        int r = mt * MT * bA + 4 * (F - gq * sub4);
+                        for (int i = 0; i < m; ++i) {
+                            S.fdig[(((size_t)mt * NF + f) * m + i) * 256 + t] = r % ext_in[i];
+                            r /= ext_in[i];
+                        }
+                    }
+            // Output offset of every block row.
+            S.fopart.assign(Mblk, 0);
+            for (int row = 0; row < Mblk; ++row) {
+                int r = row, op = 0;
+                for (int i = 0; i < m - 1; ++i) {
+                    op += (r % a.mrad[i]) * a.mos[i];
+                    r /= a.mrad[i];
+                }
+                S.fopart[row] = op;
+            }
+        }
         // Tasks.
         const int mtiles = (Mblk + S.tile.MT - 1) / S.tile.MT;
         for (int32_t gi = 0; gi < (int32_t)S.groups.size(); ++gi) {
@@ -286,6 +433,7 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err)
             for (int mt = 0; mt < mtiles; ++mt)
                 for (int nt = 0; nt < ntiles; ++nt) S.tasks.push_back(Task{gi, (int16_t)mt, (int16_t)nt});
         }
+        order_tasks_for_xcds(&S.tasks);
         if (mtiles > 32767 || S.tasks.size() > (size_t)INT32_MAX) {
             *err = "too many tasks";
             return false;
@@ -294,7 +442,7 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err)
         S.in_ws = d == 0 ? -1 : P->temp_off[k + 1];
         S.out_ws = k == 0 ? -1 : P->temp_off[k];
         S.out_elems = k == 0 ? 0 : P->temp_jtuples[k] * P->temp_prefixes[k] * P->temp_block[k];
-        if (cmp[d] == CMP_FP32) { S.xp_slot = 0; S.xp_lo_slot = -1; }
+        if (cmp[d] == CMP_FP32) { S.xp_slot = S.fast ? 3 : 0; S.xp_lo_slot = -1; }
         else if (cmp[d] == CMP_BF16) { S.xp_slot = 1; S.xp_lo_slot = -1; }
         else { S.xp_slot = 1; S.xp_lo_slot = 2; }
         P->flops += S.flops;
@@ -344,8 +492,11 @@ const Plan *plan_get(const PlanKey &key, std::string *err)
     if (!plan_build_host(key, P.get(), err)) return nullptr;
     for (auto &S : P->stages) {
         if (!upload(S.groups, &S.d_groups, err) || !upload(S.in_tab, &S.d_in_tab, err) ||
-            !upload(S.tasks, &S.d_tasks, err))
+            !upload(S.tasks, &S.d_tasks, err) || !upload(S.fdig, &S.d_fdig, err) ||
+            !upload(S.fopart, &S.d_fopart, err))
             return nullptr;   // tables of a failed plan are leaked, never used
+        S.args.fdig = S.d_fdig;
+        S.args.fopart = S.d_fopart;
         S.args.groups = S.d_groups;
         S.args.in_tab = S.d_in_tab;
         S.args.tasks = S.d_tasks;

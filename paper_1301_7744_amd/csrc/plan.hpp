@@ -22,21 +22,26 @@ std::vector<int32_t> sorted_tuples(int len, int N);
 // Tile shape of one stage launch.
 struct TileCfg {
     int MT, NT, WM, WN;
+    int KT = 16;   // K chunk of the block-copy kernel
+    int PD = 1;    // its prefetch depth (register sets of staged loads)
 };
 
 struct StagePlan {
     int d = 0;          // loop level (0 forms T^(m-1))
     int k = 0;          // contracted mode
     int compute = CMP_FP32;
+    bool fast = false;  // block-copy staging kernel (whole 256-row blocks, bA | 16)
     TileCfg tile{};
     StageArgs args{};   // everything but in/out/xp pointers
     std::vector<GroupDesc> groups;
     std::vector<InEntry> in_tab;
     std::vector<Task> tasks;
+    std::vector<int32_t> fdig, fopart;   // block-copy kernel tables (see StageArgs)
     // Device copies (owned by the plan).
     GroupDesc *d_groups = nullptr;
     InEntry *d_in_tab = nullptr;
     Task *d_tasks = nullptr;
+    int32_t *d_fdig = nullptr, *d_fopart = nullptr;
     // Where the operands live: -1 means the caller's A (input) or C (output),
     // otherwise a byte offset into the workspace.
     int64_t in_ws = -1, out_ws = -1;
@@ -52,8 +57,10 @@ struct Plan {
     int nbar = 0, pbar = 0;
     int prec = 0, in_dtype = 0;
     int64_t Kpad = 0, Ppad = 0, Kx = 0;   // Kx: row stride of the X panels
-    // X panels in the workspace: slot 0 fp32, slot 1 bf16 (rounded), slot 2 bf16 lo.
-    int64_t xp_off[3] = {-1, -1, -1};
+    int64_t Kt = 0, Pt = 0;               // transposed fp32 panel: Kt rows of Pt entries
+    // X panels in the workspace: slot 0 fp32, slot 1 bf16 (rounded), slot 2
+    // bf16 lo, all [Ppad][Kx]; slot 3 fp32 transposed [Kt][Pt]; all zero-padded.
+    int64_t xp_off[4] = {-1, -1, -1, -1};
     // Temporaries T^(k), k = 1..m-1.
     int64_t temp_off[kMaxOrder] = {};
     int temp_dtype[kMaxOrder] = {};
@@ -69,6 +76,7 @@ struct PlanKey {
     int m;
     int64_t n, p;
     int bA, bC, prec, in_dtype;
+    bool generic_only = false;   // force the generic staging kernel (testing)
     bool operator<(const PlanKey &o) const;
 };
 

@@ -312,3 +312,26 @@ def test_workspace_too_small_rejected():
                    ws.data_ptr(), need, None)
     torch.cuda.synchronize()
     assert rc == 0
+
+
+# ------------------------------------------------------------------ both staging kernels
+FAST_SHAPES = [(3, 35, 35, 16, 16), (3, 40, 24, 16, 16), (3, 100, 70, 16, 16), (5, 9, 10, 4, 4), (5, 13, 7, 4, 4)]
+
+
+@pytest.mark.parametrize("generic", [False, True], ids=["blockcopy", "generic"])
+@pytest.mark.parametrize("m,n,p,bA,bC", FAST_SHAPES)
+def test_block_copy_and_generic_kernels(m, n, p, bA, bC, generic, monkeypatch):
+    """Shapes the block-copy kernel takes (256 entries per block row, bA | 16),
+    run through it and through the generic kernel: both match the oracle."""
+    if generic:
+        monkeypatch.setenv("STTSM_GENERIC_KERNELS", "1")
+    else:
+        monkeypatch.delenv("STTSM_GENERIC_KERNELS", raising=False)
+    say("kernels", "generic" if generic else "block-copy", m, n, p, bA, bC)
+    A = synth.symmetric_uniform(m, n, (m, n, p, 91))
+    X = synth.change_of_basis(p, n, (m, n, p, 92))
+    got = run(A, X, bA, bC, P32)
+    e = err(got, ref_bcss(A.astype(np.float64), X.astype(np.float64), bC), m, p, bC)
+    say("  rel err", e)
+    assert e <= TOL_FP32
+    assert np.all(got[padding_mask(m, p, bC)] == 0.0)
