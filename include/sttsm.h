@@ -166,6 +166,72 @@ int sttsm_profile_enable(int32_t max_launches);
 int sttsm_profile_read(double *level_ms, int64_t *level_launches, int32_t max_levels, int64_t *dropped);
 int sttsm_profile_disable(void);
 
+/* ------------------------------------------------------------------ serving
+ *
+ * A server runs a continuous-batching loop over sttsm requests of mixed
+ * order and size.  Each request's state (its BCSS A, X, C, temporaries and
+ * index tables) lives in a caller-provided device arena whose size is the
+ * HBM budget; a request is admitted (first come, first served) once its
+ * footprint fits in the free arena and fewer than max_inflight requests
+ * are active.  Work proceeds in rounds: one round stages the inputs of newly
+ * admitted requests and then runs the next level (T^(m-1), ..., C) of every
+ * active request in grouped persistent launches, where all workgroups draw
+ * tiles of all requests from one shared task queue (the algorithm-by-blocks
+ * unit of work, scheduled across requests as the paper's future-work
+ * section suggests for block scheduling).  Requests that arrive while a
+ * round runs join at the next round, so their work overlaps with that of
+ * requests already on the GPU.  Each tile is computed whole (no split
+ * reductions), so a request's C is bit-identical alone and in any mix.
+ * A server owns one worker thread and one HIP stream of default priority.
+ */
+typedef struct sttsm_server sttsm_server;
+
+typedef struct {
+    bcss_layout A;        /* order, n, bA, dtype of A (C has the same order) */
+    bcss_layout C;        /* p = C.n, bC = C.b, dtype F32                     */
+    const void *A_bcss;   /* A in BCSS; must stay valid until admitted         */
+    const void *X;        /* p x n, dtype A.dtype; (j, i) at X[j*rs_x+i*cs_x]  */
+    int64_t rs_x, cs_x;
+    int32_t prec;         /* sttsm_prec                                        */
+    int32_t src_is_host;  /* 1: A_bcss and X are host pointers, else device    */
+} sttsm_request;
+
+enum { STTSM_QUEUED = 0, STTSM_ADMITTED = 1, STTSM_RUNNING = 2, STTSM_DONE = 3, STTSM_FAILED = 4 };
+
+/* arena: device memory of arena_bytes (256-byte aligned) owned by the caller
+ * and used by the server until sttsm_server_destroy returns.  EINVAL for a
+ * null arena, zero size or max_inflight < 1. */
+int sttsm_server_create(void *arena, size_t arena_bytes, int32_t max_inflight, sttsm_server **out);
+
+/* Bytes of arena a request occupies while active (its C stays until fetched). */
+size_t sttsm_request_footprint(const sttsm_request *req);
+
+/* Queues a request; never waits for the GPU.  EINVAL for a bad request,
+ * ENOMEM when its footprint exceeds the whole arena (it could never run). */
+int sttsm_submit(sttsm_server *s, const sttsm_request *req, uint64_t *ticket);
+
+/* *state <- STTSM_QUEUED .. STTSM_FAILED; ENOTFOUND for an unknown ticket. */
+int sttsm_poll(sttsm_server *s, uint64_t ticket, int32_t *state);
+
+/* Waits up to timeout_us (< 0: no limit) for the request to finish;
+ * EAGAIN on time-out, ENOTFOUND for an unknown ticket. */
+int sttsm_wait(sttsm_server *s, uint64_t ticket, int64_t timeout_us, int32_t *state);
+
+/* Copies a finished request's C (bcss_num_elems(C) floats) to C_dst and
+ * forgets the ticket.  EAGAIN if not finished, ENOTFOUND if unknown or
+ * already fetched, EHIP if the request failed (the ticket is forgotten). */
+int sttsm_fetch(sttsm_server *s, uint64_t ticket, void *C_dst, int32_t dst_is_host);
+
+/* Latency (submit -> done) percentiles and throughput of the requests
+ * completed so far; zeros when none.  Also the number of rounds run and of
+ * grouped launches made. */
+int sttsm_server_stats(sttsm_server *s, double *p50_us, double *p99_us, double *req_per_s,
+                       int64_t *completed, int64_t *rounds, int64_t *launches);
+
+/* Stops the loop after the running round; unfinished requests fail.
+ * Joins the worker and releases everything the server allocated. */
+int sttsm_server_destroy(sttsm_server *s);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char *sttsm_last_error(void);
 

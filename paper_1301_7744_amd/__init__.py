@@ -32,6 +32,15 @@ class Layout(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int64), ("b", ctypes.c_int32), ("dtype", ctypes.c_int32)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("A", Layout), ("C", Layout), ("A_bcss", ctypes.c_void_p), ("X", ctypes.c_void_p),
+                ("rs_x", ctypes.c_int64), ("cs_x", ctypes.c_int64), ("prec", ctypes.c_int32),
+                ("src_is_host", ctypes.c_int32)]
+
+
+QUEUED, ADMITTED, RUNNING, DONE, FAILED = 0, 1, 2, 3, 4
+
+
 _lib = None
 
 
@@ -62,6 +71,16 @@ def load():
         "sttsm_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32,
                                               ctypes.POINTER(i64)]),
         "sttsm_profile_disable": (ctypes.c_int, []),
+        "sttsm_request_footprint": (sz, [ctypes.POINTER(Request)]),
+        "sttsm_server_create": (ctypes.c_int, [vp, sz, i32, ctypes.POINTER(ctypes.c_void_p)]),
+        "sttsm_submit": (ctypes.c_int, [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+        "sttsm_poll": (ctypes.c_int, [vp, ctypes.c_uint64, ctypes.POINTER(i32)]),
+        "sttsm_wait": (ctypes.c_int, [vp, ctypes.c_uint64, i64, ctypes.POINTER(i32)]),
+        "sttsm_fetch": (ctypes.c_int, [vp, ctypes.c_uint64, vp, i32]),
+        "sttsm_server_stats": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
+                                              ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "sttsm_server_destroy": (ctypes.c_int, [vp]),
         "sttsm_last_error": (ctypes.c_char_p, []),
         "sttsm_version": (ctypes.c_char_p, []),
     }
@@ -76,7 +95,9 @@ def load():
 def exported_symbols():
     return ["bcss_num_blocks", "bcss_num_elems", "bcss_pack", "bcss_unpack", "sttsm_flops",
             "sttsm_workspace_bytes", "sttsm", "sttsm_workspace_temp", "sttsm_plan_info", "sttsm_profile_enable",
-            "sttsm_profile_read", "sttsm_profile_disable", "sttsm_last_error", "sttsm_version"]
+            "sttsm_profile_read", "sttsm_profile_disable", "sttsm_request_footprint", "sttsm_server_create",
+            "sttsm_submit", "sttsm_poll", "sttsm_wait", "sttsm_fetch", "sttsm_server_stats", "sttsm_server_destroy",
+            "sttsm_last_error", "sttsm_version"]
 
 
 def _check(rc: int):
@@ -234,6 +255,84 @@ def profile_read(max_levels: int = 8):
 
 def profile_disable():
     _check(load().sttsm_profile_disable())
+
+
+# ------------------------------------------------------------------ serving
+def make_request(A_bcss, X, m: int, n: int, p: int, bA: int, bC: int, prec: int) -> Request:
+    """Request struct for device tensors A (BCSS) and X (p x n, row-major)."""
+    dt = _torch_dtype_code(A_bcss)
+    if X.dtype != A_bcss.dtype or tuple(X.shape) != (p, n) or X.stride(1) != 1:
+        raise ValueError("X must be a row-major (p, n) tensor of A's dtype")
+    return Request(layout(m, n, bA, dt), layout(m, p, bC, F32), _ptr(A_bcss), X.data_ptr(), X.stride(0), 1,
+                   prec, 0)
+
+
+def request_footprint(m: int, n: int, p: int, bA: int, bC: int, prec: int, dtype: int = F32) -> int:
+    r = Request(layout(m, n, bA, dtype), layout(m, p, bC, F32), 1, 1, n, 1, prec, 0)
+    return load().sttsm_request_footprint(ctypes.byref(r))
+
+
+class Server:
+    """Continuous-batching sttsm server over a device arena of arena_bytes
+    (the HBM budget), allocated here with PyTorch."""
+
+    def __init__(self, arena_bytes: int, max_inflight: int = 64, device="cuda"):
+        import torch
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        _check(load().sttsm_server_create(self.arena.data_ptr(), self.arena.numel(), max_inflight, ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, A_bcss, X, m: int, n: int, p: int, bA: int, bC: int, prec: int) -> int:
+        req = make_request(A_bcss, X, m, n, p, bA, bC, prec)
+        t = ctypes.c_uint64()
+        _check(load().sttsm_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
+        self._keep[t.value] = (A_bcss, X, m, p, bC)   # inputs stay alive until fetched
+        return t.value
+
+    def poll(self, ticket: int) -> int:
+        st = ctypes.c_int32()
+        _check(load().sttsm_poll(self.handle, ticket, ctypes.byref(st)))
+        return st.value
+
+    def wait(self, ticket: int, timeout_s: float = -1.0) -> int:
+        st = ctypes.c_int32()
+        rc = load().sttsm_wait(self.handle, ticket, int(timeout_s * 1e6) if timeout_s >= 0 else -1, ctypes.byref(st))
+        if rc not in (0, -4):
+            _check(rc)
+        return st.value
+
+    def fetch(self, ticket: int, out=None):
+        import torch
+        if ticket not in self._keep:   # unknown or already fetched: the library says which
+            _check(load().sttsm_fetch(self.handle, ticket, 1, 0))
+        A, X, m, p, bC = self._keep[ticket]
+        nc = bcss_num_elems(m, p, bC, F32)
+        if out is None:
+            out = torch.empty(nc, dtype=torch.float32, device=A.device)
+        _check(load().sttsm_fetch(self.handle, ticket, _ptr(out), 0))
+        del self._keep[ticket]
+        return out
+
+    def stats(self) -> dict:
+        p50, p99, rps = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        c, r, l = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(load().sttsm_server_stats(self.handle, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(rps),
+                                         ctypes.byref(c), ctypes.byref(r), ctypes.byref(l)))
+        return dict(p50_us=p50.value, p99_us=p99.value, req_per_s=rps.value, completed=c.value, rounds=r.value,
+                    launches=l.value)
+
+    def close(self):
+        if self.handle:
+            _check(load().sttsm_server_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version() -> str:

@@ -10,12 +10,13 @@
 #include <string>
 #include <vector>
 
+#include "abi_util.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
 
 using namespace symt;
 
-namespace {
+namespace symt {
 
 thread_local std::string g_err;
 
@@ -46,6 +47,10 @@ bool layout_ok(const bcss_layout *L, std::string *why)
     return true;
 }
 
+}  // namespace symt
+
+namespace {
+
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 // Optional per-level timing: a pool of event pairs recorded around each
@@ -73,6 +78,10 @@ long prof_slot(int lvl)
     return (long)g_prof.used++;
 }
 
+}  // namespace
+
+namespace symt {
+
 // Validates an sttsm problem and returns its plan key.
 int make_key(const bcss_layout *A, const bcss_layout *C, int32_t prec, PlanKey *key)
 {
@@ -99,7 +108,7 @@ int make_key(const bcss_layout *A, const bcss_layout *C, int32_t prec, PlanKey *
     return STTSM_OK;
 }
 
-}  // namespace
+}  // namespace symt
 
 extern "C" {
 

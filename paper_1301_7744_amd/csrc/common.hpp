@@ -42,6 +42,17 @@ struct Task {
     int16_t nt;   // N tile index
 };
 
+// Task of the grouped persistent kernel: a tile of one (request, level) stage.
+struct GroupedTask {
+    int32_t stage;   // index into the launch's StageArgs array
+    int32_t group;
+    int16_t mt, nt;
+};
+
+// Tile of the grouped kernel (generic staging, 2x2 waves of 32x32).
+constexpr int kGroupedMT = 64;
+constexpr int kGroupedNT = 64;
+
 // Launch-wide parameters of one stage (kernel argument, passed by value).
 struct StageArgs {
     const void *in;          // input tensor (A in BCSS, or T^(k+1))

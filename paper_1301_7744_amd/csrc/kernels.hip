@@ -226,11 +226,25 @@ struct CmpTraits<CMP_X3> {
     typedef u16 L;
 };
 
-template <int CMP, int MT, int NT, int WM, int WN, bool B_IS_IN, bool FIRST>
-__global__ __launch_bounds__(256) void stage_kernel(const StageArgs a)
+// LDS of the generic tile.
+template <int CMP, int MT, int NT>
+struct GenericSmem {
+    using L = typename CmpTraits<CMP>::L;
+    static constexpr int NL = CMP == CMP_X3 ? 2 : 1;   // LDS planes (hi, lo)
+    static constexpr int LROW = CmpTraits<CMP>::LROW;
+    __attribute__((aligned(16))) L s_in[NL][2][MT * LROW];
+    __attribute__((aligned(16))) L s_x[NL][2][NT * LROW];
+    int32_t s_mpart[kMaxOrder][MT];   // input offset of row mm, per insertion position
+    int32_t s_opart[MT];              // output offset of row mm (-1: beyond Mblk)
+    int64_t s_npart[NT];              // output offset of column nn (-1: beyond N)
+};
+
+// One MT x NT tile of one row group (see the comment above); used by the
+// per-level kernel and by the grouped persistent kernel of the server.
+template <int CMP, int MT, int NT, int WM, int WN, bool B_IS_IN>
+__device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task, GenericSmem<CMP, MT, NT> &sm)
 {
     using Tr = CmpTraits<CMP>;
-    using L = typename Tr::L;
     constexpr int KT = Tr::KT, LROW = Tr::LROW, VK = Tr::VK;
     constexpr bool SPLIT = CMP == CMP_X3;
     constexpr int NL = SPLIT ? 2 : 1;            // LDS planes (hi, lo)
@@ -242,16 +256,15 @@ __global__ __launch_bounds__(256) void stage_kernel(const StageArgs a)
     constexpr int IN_PER_T = (IN_VECS + 255) / 256;
     constexpr int X_PER_T = (X_VECS + 255) / 256;
 
-    __shared__ __attribute__((aligned(16))) L s_in[NL][2][MT * LROW];
-    __shared__ __attribute__((aligned(16))) L s_x[NL][2][NT * LROW];
-    __shared__ int32_t s_mpart[kMaxOrder][MT];   // input offset of row mm, per insertion position
-    __shared__ int32_t s_opart[MT];              // output offset of row mm (-1: beyond Mblk)
-    __shared__ int64_t s_npart[NT];              // output offset of column nn (-1: beyond N)
+    auto &s_in = sm.s_in;
+    auto &s_x = sm.s_x;
+    auto &s_mpart = sm.s_mpart;
+    auto &s_opart = sm.s_opart;
+    auto &s_npart = sm.s_npart;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
-    const Task task = a.tasks[blockIdx.x];
     const GroupDesc g = a.groups[task.group];
     const int m0 = task.mt * MT, n0 = task.nt * NT;
     const int Nvalid = g.jcount * a.bC;
@@ -500,6 +513,58 @@ __global__ __launch_bounds__(256) void stage_kernel(const StageArgs a)
                     else out16[o] = f2bf(acc[i][j][r]);
                 }
             }
+}
+
+template <int CMP, int MT, int NT, int WM, int WN, bool B_IS_IN, bool FIRST>
+__global__ __launch_bounds__(256) void stage_kernel(const StageArgs a)
+{
+    __shared__ GenericSmem<CMP, MT, NT> sm;
+    generic_tile<CMP, MT, NT, WM, WN, B_IS_IN>(a, a.tasks[blockIdx.x], sm);
+}
+
+// Grouped persistent kernel: one launch runs the tasks of many (request,
+// level) stages, each task naming its stage's arguments.  Workgroups take
+// tasks from a shared queue (an atomic counter) until it is empty; tasks of
+// one launch never depend on each other, so no workgroup ever waits.
+template <int CMP, int MT, int NT, int WM, int WN>
+__global__ __launch_bounds__(256) void grouped_kernel(const StageArgs *__restrict__ stages,
+                                                      const GroupedTask *__restrict__ tasks, int ntasks,
+                                                      int *__restrict__ queue_head)
+{
+    __shared__ GenericSmem<CMP, MT, NT> sm;
+    __shared__ int s_t;
+    for (;;) {
+        if (threadIdx.x == 0) s_t = atomicAdd(queue_head, 1);
+        __syncthreads();
+        const int t = s_t;
+        __syncthreads();   // every thread has read s_t before it is reused
+        if (t >= ntasks) break;
+        const GroupedTask gt = tasks[t];
+        const StageArgs &a = stages[gt.stage];
+        const Task task{gt.group, gt.mt, gt.nt};
+        if (a.k != 0) generic_tile<CMP, MT, NT, WM, WN, true>(a, task, sm);
+        else generic_tile<CMP, MT, NT, WM, WN, false>(a, task, sm);
+        __syncthreads();   // LDS is reused by the next task
+    }
+}
+
+int launch_grouped(int compute, const StageArgs *d_stages, const GroupedTask *d_tasks, int ntasks, int *d_head,
+                   int grid, hipStream_t s)
+{
+    if (ntasks <= 0) return 0;
+    const dim3 g((unsigned)std::max(1, std::min(grid, ntasks))), b(256);
+    if (compute == CMP_FP32)
+        hipLaunchKernelGGL((grouped_kernel<CMP_FP32, kGroupedMT, kGroupedNT, 2, 2>), g, b, 0, s, d_stages, d_tasks,
+                           ntasks, d_head);
+    else if (compute == CMP_BF16)
+        hipLaunchKernelGGL((grouped_kernel<CMP_BF16, kGroupedMT, kGroupedNT, 2, 2>), g, b, 0, s, d_stages, d_tasks,
+                           ntasks, d_head);
+    else if (compute == CMP_X3)
+        hipLaunchKernelGGL((grouped_kernel<CMP_X3, kGroupedMT, kGroupedNT, 2, 2>), g, b, 0, s, d_stages, d_tasks,
+                           ntasks, d_head);
+    else
+        return -1;
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 // FIRST marks the level that reads A; it is a separate instantiation so that
@@ -766,7 +831,7 @@ static void launch_fast_t(const StageArgs &a, bool first, hipStream_t s)
 
 // Tile shapes of the block-copy kernel (MT x NT, K chunk KT, prefetch depth PD).
 #define STTSM_FAST_TILES(X) X(256, 64, 16, 1) X(256, 128, 16, 1) X(256, 32, 16, 1) X(128, 64, 16, 1) \
-    X(128, 128, 16, 1) X(256, 64, 32, 1) X(128, 64, 32, 1)
+    X(128, 128, 16, 1) X(128, 64, 32, 1)
 
 template <int M>
 static int launch_fast_m(const StageArgs &a, int MT, int NT, int KT, int PD, bool first, hipStream_t s)

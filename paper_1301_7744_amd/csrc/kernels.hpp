@@ -17,6 +17,9 @@ int launch_prep_x(int esize, const void *X, int64_t rs, int64_t cs, int64_t p, i
 int launch_stage(const StageArgs &a, int compute, int MT, bool first, hipStream_t s);
 int launch_stage_fast(const StageArgs &a, int MT, int NT, int KT, int PD, bool first, hipStream_t s);
 bool fast_tile_supported(int MT, int NT, int KT, int PD);
+// Grouped persistent launch over a task queue (*d_head must be 0).
+int launch_grouped(int compute, const StageArgs *d_stages, const GroupedTask *d_tasks, int ntasks, int *d_head,
+                   int grid, hipStream_t s);
 // Whether the block-copy kernel is instantiated for order m and nbar blocks.
 bool fast_supported(int m, int nbar);
 int launch_prep_xt(int esize, const void *X, int64_t rs, int64_t cs, int64_t p, int64_t n, int64_t Kt, int64_t Pt,

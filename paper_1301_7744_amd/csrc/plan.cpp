@@ -60,6 +60,7 @@ bool PlanKey::operator<(const PlanKey &o) const
     if (bC != o.bC) return bC < o.bC;
     if (prec != o.prec) return prec < o.prec;
     if (in_dtype != o.in_dtype) return in_dtype < o.in_dtype;
+    if (grouped != o.grouped) return grouped < o.grouped;
     return generic_only < o.generic_only;
 }
 
@@ -187,7 +188,7 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err)
             if (j != k) mblk *= (j <= k ? bA : bC);
         const int in_dt = d == 0 ? key.in_dtype : tdt[k + 1];
         fast[d] = cmp[d] == CMP_FP32 && in_dt == F32 && mblk == 256 && (bA == 4 || bA == 8 || bA == 16) &&
-                  bC % 4 == 0 && !key.generic_only && fast_supported(m, nbar);
+                  bC % 4 == 0 && !key.generic_only && !key.grouped && fast_supported(m, nbar);
     }
 
     // Workspace: X panels first.
@@ -309,7 +310,7 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err)
         for (int j = 0; j < m; ++j) a.os[j] = (int32_t)os[j];
         for (int i = 0; i < kMaxOrder; ++i) a.mos[i] = i < m - 1 ? (int32_t)os[a.mmode[i]] : 0;
         a.osk = (int32_t)os[k];
-        S.tile = choose_tile(Mblk);
+        S.tile = key.grouped ? TileCfg{kGroupedMT, kGroupedNT, 2, 2} : choose_tile(Mblk);
         S.fast = fast[d];
         for (int j = 0; j < m; ++j) {
             a.ext_in[j] = ext_in[j];

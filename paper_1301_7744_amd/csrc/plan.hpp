@@ -77,6 +77,7 @@ struct PlanKey {
     int64_t n, p;
     int bA, bC, prec, in_dtype;
     bool generic_only = false;   // force the generic staging kernel (testing)
+    bool grouped = false;        // tiles of the grouped kernel (serving)
     bool operator<(const PlanKey &o) const;
 };
 

@@ -1,0 +1,582 @@
+// Continuous-batching sttsm server (declared in include/sttsm.h).
+//
+// One worker thread runs rounds.  A round (1) admits queued requests in
+// arrival order while their footprint fits in the arena and the in-flight
+// cap allows, (2) stages the inputs and index tables of newly admitted
+// requests into their arena regions and builds their padded X panels, and
+// (3) runs the next level of every active request in grouped persistent
+// launches (one per compute form present) whose workgroups take tiles of all
+// requests from one shared queue.  Completion of the last level marks a
+// request done; its A, X, temporaries and tables are released at once and
+// its C when the caller fetches it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "abi_util.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace symt;
+
+namespace {
+
+size_t round256(size_t x) { return (x + 255) / 256 * 256; }
+
+double now_us()
+{
+    using namespace std::chrono;
+    return duration<double, std::micro>(steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over [0, total) with coalescing frees.
+struct ArenaAlloc {
+    std::map<size_t, size_t> free_;   // offset -> size
+    void init(size_t total)
+    {
+        free_.clear();
+        if (total) free_[0] = total;
+    }
+    bool alloc(size_t n, size_t *off)
+    {
+        n = round256(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            *off = it->first;
+            const size_t rest = it->second - n, o2 = it->first + n;
+            free_.erase(it);
+            if (rest) free_[o2] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t n)
+    {
+        n = round256(n);
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+// Byte layout of a request's arena regions.
+struct Footprint {
+    size_t a = 0, x = 0, ws = 0, tables = 0, main = 0, c = 0;
+    // offsets inside the main region
+    size_t off_a = 0, off_x = 0, off_ws = 0, off_tab = 0;
+    std::vector<size_t> off_groups, off_in;   // per level, inside the table area
+};
+
+struct Req {
+    uint64_t ticket = 0;
+    int state = STTSM_QUEUED;
+    sttsm_request r{};
+    std::unique_ptr<Plan> plan;
+    Footprint fp;
+    size_t off_main = 0, off_c = 0;
+    char *main = nullptr, *C = nullptr;
+    int level = -1;            // next level to run; m when done
+    double t_submit = 0, t_done = 0;
+};
+
+int compute_footprint(const sttsm_request *q, const Plan &P, Footprint *fp)
+{
+    const int64_t na = bcss_num_elems(&q->A), nc = bcss_num_elems(&q->C);
+    if (na < 0 || nc < 0) return STTSM_EINVAL;
+    fp->a = round256((size_t)na * dtype_size(q->A.dtype));
+    fp->x = round256((size_t)(q->C.n * q->A.n) * dtype_size(q->A.dtype));
+    fp->ws = round256(P.ws_bytes);
+    fp->tables = 0;
+    fp->off_groups.clear();
+    fp->off_in.clear();
+    for (const StagePlan &S : P.stages) {
+        fp->off_groups.push_back(fp->tables);
+        fp->tables += round256(S.groups.size() * sizeof(GroupDesc));
+        fp->off_in.push_back(fp->tables);
+        fp->tables += round256(S.in_tab.size() * sizeof(InEntry));
+    }
+    fp->off_a = 0;
+    fp->off_x = fp->a;
+    fp->off_ws = fp->off_x + fp->x;
+    fp->off_tab = fp->off_ws + fp->ws;
+    fp->main = fp->off_tab + fp->tables;
+    fp->c = round256((size_t)nc * 4);
+    return STTSM_OK;
+}
+
+}  // namespace
+
+struct sttsm_server {
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    int max_inflight = 1;
+    int device = 0;
+    int grid = 512;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Req *> arrival;
+    std::vector<Req *> active;
+    std::map<uint64_t, std::unique_ptr<Req>> all;
+    ArenaAlloc alloc;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::string fatal;
+    // device side of the rounds
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    StageArgs *d_stages = nullptr;
+    GroupedTask *d_tasks = nullptr;
+    int *d_heads = nullptr;
+    size_t cap_stages = 0, cap_tasks = 0;
+    StageArgs *h_stages = nullptr;   // pinned staging
+    GroupedTask *h_tasks = nullptr;
+    // statistics
+    std::vector<double> lat_us;
+    double t_first_submit = -1, t_last_done = 0;
+    int64_t rounds = 0, launches = 0;
+    std::thread worker;
+};
+
+namespace {
+
+bool ensure_capacity(sttsm_server *S, size_t nstages, size_t ntasks, std::string *err)
+{
+    if (nstages > S->cap_stages) {
+        const size_t cap = std::max(nstages, 2 * S->cap_stages);
+        if (S->d_stages) (void)hipFree(S->d_stages);
+        if (S->h_stages) (void)hipHostFree(S->h_stages);
+        S->d_stages = nullptr;
+        S->h_stages = nullptr;
+        if (hipMalloc((void **)&S->d_stages, cap * sizeof(StageArgs)) != hipSuccess ||
+            hipHostMalloc((void **)&S->h_stages, cap * sizeof(StageArgs), hipHostMallocDefault) != hipSuccess) {
+            *err = "server: cannot allocate stage table";
+            S->cap_stages = 0;
+            return false;
+        }
+        S->cap_stages = cap;
+    }
+    if (ntasks > S->cap_tasks) {
+        const size_t cap = std::max(ntasks, 2 * S->cap_tasks);
+        if (S->d_tasks) (void)hipFree(S->d_tasks);
+        if (S->h_tasks) (void)hipHostFree(S->h_tasks);
+        S->d_tasks = nullptr;
+        S->h_tasks = nullptr;
+        if (hipMalloc((void **)&S->d_tasks, cap * sizeof(GroupedTask)) != hipSuccess ||
+            hipHostMalloc((void **)&S->h_tasks, cap * sizeof(GroupedTask), hipHostMallocDefault) != hipSuccess) {
+            *err = "server: cannot allocate task queue";
+            S->cap_tasks = 0;
+            return false;
+        }
+        S->cap_tasks = cap;
+    }
+    return true;
+}
+
+// Copies a newly admitted request's inputs and tables into its region and
+// builds its X panels (all on the server stream).
+bool stage_inputs(sttsm_server *S, Req *q, std::string *err)
+{
+    const sttsm_request &r = q->r;
+    const Footprint &fp = q->fp;
+    const hipMemcpyKind kin = r.src_is_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    const int es = dtype_size(r.A.dtype);
+    const int64_t na = bcss_num_elems(&r.A);
+    if (hipMemcpyAsync(q->main + fp.off_a, r.A_bcss, (size_t)na * es, kin, S->stream) != hipSuccess) {
+        *err = "server: copy of A failed";
+        return false;
+    }
+    // X is repacked contiguous (rs = n, cs = 1)
+    const int64_t p = r.C.n, n = r.A.n;
+    if (hipMemcpy2DAsync(q->main + fp.off_x, (size_t)n * es, r.X, (size_t)r.rs_x * es, (size_t)n * es, (size_t)p,
+                         kin, S->stream) != hipSuccess || r.cs_x != 1) {
+        if (r.cs_x != 1) *err = "server: X must have unit column stride";
+        else *err = "server: copy of X failed";
+        return false;
+    }
+    for (size_t d = 0; d < q->plan->stages.size(); ++d) {
+        const StagePlan &St = q->plan->stages[d];
+        char *tab = q->main + fp.off_tab;
+        if (!St.groups.empty() &&
+            hipMemcpyAsync(tab + fp.off_groups[d], St.groups.data(), St.groups.size() * sizeof(GroupDesc),
+                           hipMemcpyHostToDevice, S->stream) != hipSuccess) {
+            *err = "server: copy of tables failed";
+            return false;
+        }
+        if (!St.in_tab.empty() &&
+            hipMemcpyAsync(tab + fp.off_in[d], St.in_tab.data(), St.in_tab.size() * sizeof(InEntry),
+                           hipMemcpyHostToDevice, S->stream) != hipSuccess) {
+            *err = "server: copy of tables failed";
+            return false;
+        }
+    }
+    const Plan &P = *q->plan;
+    char *w = q->main + fp.off_ws;
+    float *x32 = P.xp_off[0] >= 0 ? (float *)(w + P.xp_off[0]) : nullptr;
+    uint16_t *xhi = P.xp_off[1] >= 0 ? (uint16_t *)(w + P.xp_off[1]) : nullptr;
+    uint16_t *xlo = P.xp_off[2] >= 0 ? (uint16_t *)(w + P.xp_off[2]) : nullptr;
+    if ((x32 || xhi || xlo) && launch_prep_x(es, q->main + fp.off_x, n, 1, p, n, P.Ppad, P.Kx, x32, xhi, xlo, S->stream)) {
+        *err = "server: X panel launch failed";
+        return false;
+    }
+    // The pageable host sources must be read before submit's caller may free
+    // them; host copies are staged by the runtime before the call returns.
+    return true;
+}
+
+StageArgs stage_args_for(const Req *q, int d)
+{
+    const Plan &P = *q->plan;
+    const StagePlan &St = P.stages[d];
+    const Footprint &fp = q->fp;
+    StageArgs a = St.args;
+    char *w = q->main + fp.off_ws;
+    const void *slot[3] = {P.xp_off[0] >= 0 ? w + P.xp_off[0] : nullptr, P.xp_off[1] >= 0 ? w + P.xp_off[1] : nullptr,
+                           P.xp_off[2] >= 0 ? w + P.xp_off[2] : nullptr};
+    a.in = St.in_ws < 0 ? (const void *)(q->main + fp.off_a) : (const void *)(w + St.in_ws);
+    a.out = St.out_ws < 0 ? (void *)q->C : (void *)(w + St.out_ws);
+    a.xp = slot[St.xp_slot];
+    a.xp_lo = St.xp_lo_slot >= 0 ? slot[St.xp_lo_slot] : nullptr;
+    a.groups = (const GroupDesc *)(q->main + fp.off_tab + fp.off_groups[d]);
+    a.in_tab = (const InEntry *)(q->main + fp.off_tab + fp.off_in[d]);
+    a.tasks = nullptr;
+    return a;
+}
+
+void release_main(sttsm_server *S, Req *q)
+{
+    if (q->main) S->alloc.release(q->off_main, q->fp.main);
+    q->main = nullptr;
+}
+
+void release_c(sttsm_server *S, Req *q)
+{
+    if (q->C) S->alloc.release(q->off_c, q->fp.c);
+    q->C = nullptr;
+}
+
+void fail_active(sttsm_server *S, const std::string &why)
+{
+    for (Req *q : S->active) {
+        q->state = STTSM_FAILED;
+        release_main(S, q);
+        release_c(S, q);
+    }
+    S->active.clear();
+    S->fatal = why;
+    S->cv_done.notify_all();
+}
+
+void worker_loop(sttsm_server *S)
+{
+    (void)hipSetDevice(S->device);
+    std::string err;
+    for (;;) {
+        std::vector<Req *> fresh, active;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv_work.wait(lk, [&] { return S->stop || !S->arrival.empty() || !S->active.empty(); });
+            if (S->stop) {
+                for (Req *q : S->arrival) q->state = STTSM_FAILED;
+                S->arrival.clear();
+                fail_active(S, "server stopped");
+                return;
+            }
+            // Admission: first come, first served, within the arena and the cap.
+            while (!S->arrival.empty() && (int)S->active.size() < S->max_inflight) {
+                Req *q = S->arrival.front();
+                size_t om = 0, oc = 0;
+                if (!S->alloc.alloc(q->fp.main, &om)) break;
+                if (!S->alloc.alloc(q->fp.c, &oc)) {
+                    S->alloc.release(om, q->fp.main);
+                    break;
+                }
+                q->off_main = om;
+                q->off_c = oc;
+                q->main = S->arena + om;
+                q->C = S->arena + oc;
+                q->state = STTSM_ADMITTED;
+                S->arrival.pop_front();
+                S->active.push_back(q);
+                fresh.push_back(q);
+            }
+            active = S->active;
+        }
+        if (active.empty()) {
+            // nothing fits yet although requests wait: a finished C is
+            // holding the arena until fetched; sleep until something changes
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+            continue;
+        }
+        bool ok = true;
+        for (Req *q : fresh)
+            if (!stage_inputs(S, q, &err)) { ok = false; break; }
+        // Next level of every active request, grouped by compute form.
+        size_t nst = active.size(), ntk = 0;
+        for (Req *q : active) {
+            if (q->level < 0) q->level = 0;
+            ntk += q->plan->stages[q->level].tasks.size();
+        }
+        if (ok) ok = ensure_capacity(S, nst, ntk, &err);
+        int nl = 0;
+        if (ok) {
+            size_t ti = 0;
+            for (int cmp = CMP_FP32; cmp <= CMP_X3 && ok; ++cmp) {
+                const size_t t0 = ti;
+                for (size_t i = 0; i < active.size(); ++i) {
+                    const Req *q = active[i];
+                    const StagePlan &St = q->plan->stages[q->level];
+                    if (St.compute != cmp) continue;
+                    S->h_stages[i] = stage_args_for(q, q->level);
+                    for (const Task &t : St.tasks) S->h_tasks[ti++] = GroupedTask{(int32_t)i, t.group, t.mt, t.nt};
+                }
+                if (ti == t0) continue;
+                // stage args for this launch were written above; copy once below
+                (void)t0;
+            }
+            if (hipMemcpyAsync(S->d_stages, S->h_stages, nst * sizeof(StageArgs), hipMemcpyHostToDevice, S->stream) !=
+                    hipSuccess ||
+                hipMemcpyAsync(S->d_tasks, S->h_tasks, ntk * sizeof(GroupedTask), hipMemcpyHostToDevice, S->stream) !=
+                    hipSuccess ||
+                hipMemsetAsync(S->d_heads, 0, 3 * sizeof(int), S->stream) != hipSuccess) {
+                ok = false;
+                err = "server: upload of the round failed";
+            }
+            // launch one grouped kernel per compute form, over its task range
+            size_t t0 = 0;
+            for (int cmp = CMP_FP32; cmp <= CMP_X3 && ok; ++cmp) {
+                size_t cnt = 0;
+                for (const Req *q : active)
+                    if (q->plan->stages[q->level].compute == cmp) cnt += q->plan->stages[q->level].tasks.size();
+                if (!cnt) continue;
+                if (launch_grouped(cmp, S->d_stages, S->d_tasks + t0, (int)cnt, S->d_heads + cmp, S->grid,
+                                   S->stream)) {
+                    ok = false;
+                    err = "server: grouped launch failed";
+                }
+                t0 += cnt;
+                ++nl;
+            }
+        }
+        if (ok && (hipEventRecord(S->ev, S->stream) != hipSuccess || hipEventSynchronize(S->ev) != hipSuccess)) {
+            ok = false;
+            err = std::string("server: round failed: ") + hipGetErrorString(hipGetLastError());
+        }
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (!ok) {
+            fail_active(S, err);
+            continue;
+        }
+        ++S->rounds;
+        S->launches += nl;
+        const double t = now_us();
+        std::vector<Req *> still;
+        for (Req *q : active) {
+            q->state = STTSM_RUNNING;
+            if (++q->level == q->r.A.m) {
+                q->state = STTSM_DONE;
+                q->t_done = t;
+                release_main(S, q);
+                S->lat_us.push_back(t - q->t_submit);
+                S->t_last_done = t;
+            } else {
+                still.push_back(q);
+            }
+        }
+        S->active.swap(still);
+        S->cv_done.notify_all();
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sttsm_request_footprint(const sttsm_request *req)
+{
+    if (!req) return 0;
+    PlanKey key;
+    if (make_key(&req->A, &req->C, req->prec, &key) != STTSM_OK) return 0;
+    key.grouped = true;
+    key.generic_only = false;
+    Plan P;
+    std::string why;
+    if (!plan_build_host(key, &P, &why)) return 0;
+    Footprint fp;
+    if (compute_footprint(req, P, &fp) != STTSM_OK) return 0;
+    return fp.main + fp.c;
+}
+
+int sttsm_server_create(void *arena, size_t arena_bytes, int32_t max_inflight, sttsm_server **out)
+{
+    if (!out) return fail(STTSM_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!arena || arena_bytes < 256) return fail(STTSM_EINVAL, "arena must be non-null and hold >= 256 bytes");
+    if (((uintptr_t)arena & 255) != 0) return fail(STTSM_EINVAL, "arena must be 256-byte aligned");
+    if (max_inflight < 1) return fail(STTSM_EINVAL, "max_inflight must be >= 1");
+    std::unique_ptr<sttsm_server> S(new sttsm_server);
+    S->arena = (char *)arena;
+    S->arena_bytes = arena_bytes / 256 * 256;
+    S->max_inflight = max_inflight;
+    S->alloc.init(S->arena_bytes);
+    if (hipGetDevice(&S->device) != hipSuccess) return fail(STTSM_EHIP, "hipGetDevice failed");
+    int cus = 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device) == hipSuccess && cus > 0)
+        S->grid = 2 * cus;
+    if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(STTSM_EHIP, "hipStreamCreate failed");
+    if (hipEventCreateWithFlags(&S->ev, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc((void **)&S->d_heads, 4 * sizeof(int)) != hipSuccess) {
+        (void)hipStreamDestroy(S->stream);
+        return fail(STTSM_EHIP, "server: cannot create event or queue heads");
+    }
+    sttsm_server *raw = S.release();
+    raw->worker = std::thread(worker_loop, raw);
+    *out = raw;
+    return STTSM_OK;
+}
+
+int sttsm_submit(sttsm_server *S, const sttsm_request *req, uint64_t *ticket)
+{
+    if (!S || !req || !ticket) return fail(STTSM_EINVAL, "null argument");
+    if (!req->A_bcss || !req->X) return fail(STTSM_EINVAL, "null A or X");
+    if (req->cs_x != 1 || req->rs_x < req->A.n) return fail(STTSM_EINVAL, "X must be row-major with unit column stride");
+    PlanKey key;
+    int rc = make_key(&req->A, &req->C, req->prec, &key);
+    if (rc != STTSM_OK) return rc;
+    key.grouped = true;
+    key.generic_only = false;
+    std::unique_ptr<Req> q(new Req);
+    q->r = *req;
+    q->plan.reset(new Plan);
+    std::string why;
+    if (!plan_build_host(key, q->plan.get(), &why)) return fail(STTSM_EINVAL, why);
+    if ((rc = compute_footprint(req, *q->plan, &q->fp)) != STTSM_OK) return fail(rc, "bad request layout");
+    if (q->fp.main + q->fp.c > S->arena_bytes)
+        return fail(STTSM_ENOMEM, "request footprint exceeds the whole arena");
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return fail(STTSM_EINVAL, "server is stopping");
+    q->ticket = S->next_ticket++;
+    q->t_submit = now_us();
+    if (S->t_first_submit < 0) S->t_first_submit = q->t_submit;
+    *ticket = q->ticket;
+    S->arrival.push_back(q.get());
+    S->all.emplace(q->ticket, std::move(q));
+    S->cv_work.notify_one();
+    return STTSM_OK;
+}
+
+int sttsm_poll(sttsm_server *S, uint64_t ticket, int32_t *state)
+{
+    if (!S || !state) return fail(STTSM_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return fail(STTSM_ENOTFOUND, "unknown ticket");
+    *state = it->second->state;
+    return STTSM_OK;
+}
+
+int sttsm_wait(sttsm_server *S, uint64_t ticket, int64_t timeout_us, int32_t *state)
+{
+    if (!S || !state) return fail(STTSM_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return fail(STTSM_ENOTFOUND, "unknown ticket");
+    Req *q = it->second.get();
+    auto done = [&] { return q->state == STTSM_DONE || q->state == STTSM_FAILED; };
+    if (timeout_us < 0) S->cv_done.wait(lk, done);
+    else if (!S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done)) {
+        *state = q->state;
+        return fail(STTSM_EAGAIN, "not finished");
+    }
+    *state = q->state;
+    return STTSM_OK;
+}
+
+int sttsm_fetch(sttsm_server *S, uint64_t ticket, void *C_dst, int32_t dst_is_host)
+{
+    if (!S || !C_dst) return fail(STTSM_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return fail(STTSM_ENOTFOUND, "unknown or already fetched ticket");
+    Req *q = it->second.get();
+    if (q->state == STTSM_FAILED) {
+        S->all.erase(it);
+        return fail(STTSM_EHIP, "request failed: " + S->fatal);
+    }
+    if (q->state != STTSM_DONE) return fail(STTSM_EAGAIN, "not finished");
+    const size_t bytes = (size_t)bcss_num_elems(&q->r.C) * 4;
+    const hipError_t e =
+        hipMemcpy(C_dst, q->C, bytes, dst_is_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice);
+    release_c(S, q);
+    S->all.erase(it);
+    S->cv_work.notify_one();   // freed arena may admit waiting requests
+    if (e != hipSuccess) return fail(STTSM_EHIP, "copy of C failed");
+    return STTSM_OK;
+}
+
+int sttsm_server_stats(sttsm_server *S, double *p50_us, double *p99_us, double *req_per_s, int64_t *completed,
+                       int64_t *rounds, int64_t *launches)
+{
+    if (!S) return fail(STTSM_EINVAL, "null server");
+    std::lock_guard<std::mutex> lk(S->mu);
+    std::vector<double> v = S->lat_us;
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double f) {
+        if (v.empty()) return 0.0;
+        size_t i = (size_t)(f * (double)(v.size() - 1) + 0.5);
+        return v[std::min(i, v.size() - 1)];
+    };
+    if (p50_us) *p50_us = pct(0.50);
+    if (p99_us) *p99_us = pct(0.99);
+    if (req_per_s)
+        *req_per_s = v.empty() || S->t_last_done <= S->t_first_submit
+                         ? 0.0
+                         : (double)v.size() / ((S->t_last_done - S->t_first_submit) * 1e-6);
+    if (completed) *completed = (int64_t)v.size();
+    if (rounds) *rounds = S->rounds;
+    if (launches) *launches = S->launches;
+    return STTSM_OK;
+}
+
+int sttsm_server_destroy(sttsm_server *S)
+{
+    if (!S) return fail(STTSM_EINVAL, "null server");
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv_work.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    (void)hipStreamSynchronize(S->stream);
+    if (S->d_stages) (void)hipFree(S->d_stages);
+    if (S->d_tasks) (void)hipFree(S->d_tasks);
+    if (S->d_heads) (void)hipFree(S->d_heads);
+    if (S->h_stages) (void)hipHostFree(S->h_stages);
+    if (S->h_tasks) (void)hipHostFree(S->h_tasks);
+    (void)hipEventDestroy(S->ev);
+    (void)hipStreamDestroy(S->stream);
+    delete S;
+    return STTSM_OK;
+}
+
+}  // extern "C"

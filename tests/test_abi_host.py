@@ -108,3 +108,28 @@ def test_bf16_input_needs_bf16_form():
     with pytest.raises(st.SttsmError):
         st.sttsm_plan_info(3, 8, 8, 2, 2, st.PREC_FP32, 0, dtype=st.BF16)
     assert st.sttsm_plan_info(3, 8, 8, 2, 2, st.PREC_BF16, 0, dtype=st.BF16)["groups"] > 0
+
+
+# ------------------------------------------------------------------ serving (host side)
+def test_server_argument_validation():
+    lib = st.load()
+    h = ctypes.c_void_p()
+    assert lib.sttsm_server_create(None, 1 << 20, 4, ctypes.byref(h)) == -1
+    assert lib.sttsm_server_create(256, 1 << 20, 0, ctypes.byref(h)) == -1
+    assert lib.sttsm_server_create(257, 1 << 20, 4, ctypes.byref(h)) == -1
+    t = ctypes.c_uint64()
+    assert lib.sttsm_submit(None, None, ctypes.byref(t)) == -1
+    assert lib.sttsm_poll(None, 1, ctypes.byref(ctypes.c_int32())) == -1
+    assert lib.sttsm_server_destroy(None) == -1
+
+
+def test_request_footprint():
+    """Footprint = A + X + workspace + tables + C, growing with the shape;
+    invalid requests report 0."""
+    f1 = st.request_footprint(3, 32, 32, 8, 8, st.PREC_BF16, st.BF16)
+    f2 = st.request_footprint(3, 64, 32, 8, 8, st.PREC_BF16, st.BF16)
+    f3 = st.request_footprint(4, 64, 32, 8, 8, st.PREC_BF16, st.BF16)
+    assert 0 < f1 < f2 < f3
+    ws = st.sttsm_workspace_bytes(3, 64, 32, 8, 8, st.PREC_BF16, st.BF16)
+    assert f2 > ws + st.bcss_num_elems(3, 32, 8) * 4
+    assert st.request_footprint(0, 64, 32, 8, 8, st.PREC_BF16, st.BF16) == 0
