@@ -24,6 +24,24 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3_fp32": 2500.0, "bf16x3_bf1
 PEAK_HBM_GBS = 8000.0
 
 
+def measured_traffic(workload, prec, level):
+    """HBM bytes per launch of a level's kernel from the committed rocprofv3
+    counter summary, or None when there is none or the kernel source has
+    changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, prec))
+    src = os.path.join(ROOT, "paper_1301_7744_amd", "csrc", "kernels.hip")
+    try:
+        d = json.load(open(path))
+        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if d.get("kernels_hip_sha256") != cur:
+            return None
+        e = d["per_level"][str(level)]
+        return int(e["fetch_bytes"] + e["write_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -33,11 +51,142 @@ def parse():
     ap.add_argument("--workload", default="m3_n256_b16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum oracle time for the CPU baseline")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="before timing, copy this many MiB device to device once (a plain copy kernel of known "
+                         "size, for scaling hardware byte counters)")
+    ap.add_argument("--serve", action="store_true", help="run the served mixed-request stream instead")
+    ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--serve-window", type=int, default=64, help="outstanding requests in the saturation run")
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     return ap.parse_args()
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def serve_bench(args):
+    """Served stream: m in {3,4}, n in [32,256], p in [16,n], b = 16 if n >= 128
+    else 8, BF16 inputs, FP32 accumulation and output, HBM budget 64 GB.
+    (1) saturation: closed loop with a window of outstanding requests gives
+    lambda_max; (2) Poisson arrivals at 0.5 and 0.9 lambda_max; (3) the plain
+    path, one request at a time on the same arrivals (FIFO), as baseline."""
+    import numpy as np
+    import torch
+    import paper_1301_7744_amd as st
+    import synth
+
+    N = args.serve_requests
+    shapes = synth.served_stream(N, 11, 1.0)
+    flops = np.array([st.sttsm_flops(r["m"], r["n"], r["p"], r["b"], r["b"]) for r in shapes], dtype=np.float64)
+    bf = torch.bfloat16
+
+    def inputs(r):
+        A = st.bcss_fill_hashed(r["m"], r["n"], r["b"], seed=r["seed_a"], dtype=bf)
+        X = torch.from_numpy(synth.change_of_basis(r["p"], r["n"], r["seed_x"])).to(bf).cuda()
+        return A, X
+
+    budget = int(args.serve_budget_gb * 2 ** 30)
+
+    def run(arrivals, window):
+        """Submit in arrival order (open loop: at the arrival times; closed
+        loop: keeping `window` outstanding); returns wall time and stats."""
+        srv = st.Server(budget, max_inflight=256)
+        pending = []
+        t0 = time.perf_counter()
+
+        def drain(block):
+            while pending:
+                t = pending[0]
+                st_ = srv.wait(t, -1.0 if block else 0.0)
+                if st_ not in (st.DONE, st.FAILED):
+                    return
+                if st_ == st.FAILED:
+                    raise RuntimeError("served request failed")
+                srv.fetch(t)
+                pending.pop(0)
+
+        for i, r in enumerate(shapes):
+            if arrivals is not None:
+                while time.perf_counter() - t0 < arrivals[i]:
+                    drain(False)
+                    time.sleep(0.0002)
+            else:
+                while len(pending) >= window:
+                    drain(True)
+            A, X = inputs(r)
+            pending.append(srv.submit(A, X, r["m"], r["n"], r["p"], r["b"], r["b"], st.PREC_BF16))
+            drain(False)
+        while pending:
+            drain(True)
+        wall = time.perf_counter() - t0
+        s_ = srv.stats()
+        srv.close()
+        return wall, s_
+
+    log("serve: warmup")
+    keep = shapes
+    shapes = keep[:32]
+    run(None, 16)
+    shapes = keep
+    log("serve: saturation, window", args.serve_window)
+    wall, sat = run(None, args.serve_window)
+    lam = N / wall
+    log("serve: lambda_max %.1f req/s, %.1f GFLOP/s" % (lam, flops.sum() / wall / 1e9))
+    out = {"saturated": {"req_per_s": round(lam, 2), "gflop_per_s": round(flops.sum() / wall / 1e9, 1),
+                         "p50_ms": round(sat["p50_us"] / 1e3, 3), "p99_ms": round(sat["p99_us"] / 1e3, 3),
+                         "rounds": sat["rounds"], "launches": sat["launches"]}}
+    g = synth.rng(12)
+    gaps = g.exponential(1.0, size=N)
+    for rho in (0.5, 0.9):
+        arr = np.cumsum(gaps) / (rho * lam)
+        log("serve: Poisson at %.1f lambda_max" % rho)
+        wall, s_ = run(arr, 0)
+        out["load_%.1f" % rho] = {"offered_req_per_s": round(rho * lam, 2), "req_per_s": round(N / wall, 2),
+                                  "p50_ms": round(s_["p50_us"] / 1e3, 3), "p99_ms": round(s_["p99_us"] / 1e3, 3),
+                                  "rounds": s_["rounds"]}
+        out["load_%.1f" % rho]["_arrivals"] = arr
+    # Plain path: each request alone, timed with events, then a FIFO queue
+    # over the same arrivals.
+    log("serve: plain path, one request at a time")
+    dur = np.zeros(N)
+    stream = torch.cuda.current_stream()
+    for i, r in enumerate(shapes):
+        A, X = inputs(r)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        C, ws = st.sttsm(A, X, r["m"], r["n"], r["p"], r["b"], r["b"], st.PREC_BF16)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        dur[i] = e0.elapsed_time(e1) * 1e-3
+        del A, X, C, ws
+    plain = {"req_per_s_saturated": round(N / dur.sum(), 2), "gflop_per_s": round(flops.sum() / dur.sum() / 1e9, 1)}
+    for rho in (0.5, 0.9):
+        arr = out["load_%.1f" % rho].pop("_arrivals")
+        t_free, lat = 0.0, np.zeros(N)
+        for i in range(N):
+            start = max(arr[i], t_free)
+            t_free = start + dur[i]
+            lat[i] = t_free - arr[i]
+        plain["load_%.1f" % rho] = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                                    "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                                    "req_per_s": round(N / t_free, 2)}
+    res = {
+        "metric": "served sttsm stream: requests/s and p50/p99 latency (continuous batching)",
+        "value": out["saturated"]["req_per_s"],
+        "unit": "req/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic (m in {3,4}, n in [32,256], p in [16,n], hashed symmetric A, X N(0,1)/sqrt(n))",
+        "config": {"workload": "served_mixed_stream", "requests": N, "budget_gb": args.serve_budget_gb,
+                   "window": args.serve_window, "total_gflop": round(flops.sum() / 1e9, 1)},
+        "served": out,
+        "plain_one_at_a_time": plain,
+    }
+    print(json.dumps(res), flush=True)
 
 
 def main():
@@ -46,6 +195,9 @@ def main():
         print("bench.py measures one GPU only: the sttsm path here is built and timed on a single MI355X; "
               "multi-GPU sharding is a design note, not a measured configuration.", file=sys.stderr)
         sys.exit(2)
+
+    if args.serve:
+        return serve_bench(args)
 
     import numpy as np
     import torch
@@ -57,6 +209,14 @@ def main():
     prec = st.PREC_NAMES[args.prec]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.calibrate_copy_mb > 0:
+        src = torch.ones(args.calibrate_copy_mb * 2 ** 20 // 4, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: calibration copy of %d MiB done" % args.calibrate_copy_mb)
+        del src, dst
 
     log("bench: generating inputs", args.workload)
     A_np, X_np = synth.make_config_inputs(args.workload)
@@ -118,7 +278,8 @@ def main():
                    "flops_per_step": flops, "mfma_roofline_frac": round(gflops / (peak * 1e3), 4),
                    "level_us": level_times},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "frac": round(achieved / peak, 4),
+                     "traffic": measured_traffic(args.workload, args.prec, dom),
                      "kernel": "stage_kernel level %d (%d GFLOP/launch)" % (dom, levels[dom]["flops"] // 10 ** 9),
                      "kernel_us": round(dom_ms * 1e3, 3)},
     }

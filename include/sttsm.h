@@ -101,6 +101,14 @@ int bcss_pack(const bcss_layout *L, const void *dense, void *bcss, void *stream)
  * padding is dropped.  Same buffer sizes as bcss_pack. */
 int bcss_unpack(const bcss_layout *L, const void *bcss, void *dense, void *stream);
 
+/* Fills a BCSS tensor with a symmetric pseudo-random tensor, for tests and
+ * benchmarks that cannot afford a dense original: the entry with sorted
+ * index s_0 <= ... <= s_{m-1} is lo + (hi - lo) u, u = (h >> 40) 2^-24,
+ * h = f(...f(f(seed) ^ s_0)...) ^ s_{m-1}) with f the SplitMix64 finaliser
+ * (Steele, Lea, Flood 2014), rounded to L->dtype (nearest, ties to even);
+ * padding entries are zero.  Asynchronous on `stream`. */
+int bcss_fill_hashed(const bcss_layout *L, uint64_t seed, double lo, double hi, void *bcss, void *stream);
+
 /* Symmetry-aware flop count of sttsm (Table 2, BCSS computation row, at the
  * padded sizes nbar*bA and pbar*bC); -1 on bad layouts. */
 int64_t sttsm_flops(const bcss_layout *A, const bcss_layout *C);

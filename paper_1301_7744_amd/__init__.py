@@ -61,6 +61,7 @@ def load():
         "bcss_pack": (ctypes.c_int, [L, vp, vp, vp]),
         "bcss_unpack": (ctypes.c_int, [L, vp, vp, vp]),
         "sttsm_flops": (i64, [L, L]),
+        "bcss_fill_hashed": (ctypes.c_int, [L, ctypes.c_uint64, ctypes.c_double, ctypes.c_double, vp, vp]),
         "sttsm_workspace_bytes": (sz, [L, L, i32]),
         "sttsm": (ctypes.c_int, [L, vp, vp, i64, i64, L, vp, i32, vp, sz, vp]),
         "sttsm_workspace_temp": (ctypes.c_int, [L, L, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(i32),
@@ -93,7 +94,7 @@ def load():
 
 
 def exported_symbols():
-    return ["bcss_num_blocks", "bcss_num_elems", "bcss_pack", "bcss_unpack", "sttsm_flops",
+    return ["bcss_num_blocks", "bcss_num_elems", "bcss_pack", "bcss_unpack", "bcss_fill_hashed", "sttsm_flops",
             "sttsm_workspace_bytes", "sttsm", "sttsm_workspace_temp", "sttsm_plan_info", "sttsm_profile_enable",
             "sttsm_profile_read", "sttsm_profile_disable", "sttsm_request_footprint", "sttsm_server_create",
             "sttsm_submit", "sttsm_poll", "sttsm_wait", "sttsm_fetch", "sttsm_server_stats", "sttsm_server_destroy",
@@ -182,6 +183,20 @@ def bcss_pack(dense, m: int, n: int, b: int, out=None, stream=None):
     elif out.numel() < ne or out.dtype != dense.dtype:
         raise ValueError("output too small or of the wrong dtype")
     _check(load().bcss_pack(ctypes.byref(layout(m, n, b, dt)), _ptr(dense), _ptr(out), _stream(stream)))
+    return out
+
+
+def bcss_fill_hashed(m: int, n: int, b: int, seed: int, dtype=None, lo: float = -1.0, hi: float = 1.0, out=None,
+                     stream=None, device="cuda"):
+    """BCSS tensor of a symmetric pseudo-random tensor (hashed sorted index)."""
+    import torch
+    tdt = dtype or torch.float32
+    dt = {torch.float32: F32, torch.bfloat16: BF16, torch.float64: F64}[tdt]
+    ne = bcss_num_elems(m, n, b, dt)
+    if out is None:
+        out = torch.empty(ne, dtype=tdt, device=device)
+    _check(load().bcss_fill_hashed(ctypes.byref(layout(m, n, b, dt)), int(seed) & (2 ** 64 - 1), lo, hi, _ptr(out),
+                                   _stream(stream)))
     return out
 
 

@@ -166,6 +166,21 @@ int bcss_unpack(const bcss_layout *L, const void *bcss, void *dense, void *strea
     return STTSM_OK;
 }
 
+int bcss_fill_hashed(const bcss_layout *L, uint64_t seed, double lo, double hi, void *bcss, void *stream)
+{
+    std::string why;
+    if (!layout_ok(L, &why)) return fail(STTSM_EINVAL, why);
+    if (!bcss) return fail(STTSM_EINVAL, "null buffer");
+    if (bcss_num_elems(L) < 0) return fail(STTSM_EINVAL, "BCSS size overflows");
+    const int nbar = (int)((L->n + L->b - 1) / L->b);
+    const MetaTable *T = meta_get(L->m, nbar, L->b, &why);
+    if (!T) return fail(STTSM_ENOMEM, why);
+    if (launch_fill_hashed(dtype_size(L->dtype), bcss, L->m, L->n, L->b, bcss_num_blocks(L->m, nbar), T->d_tuples,
+                           seed, lo, hi, as_stream(stream)))
+        return fail(STTSM_EHIP, std::string("fill launch failed: ") + hipGetErrorString(hipGetLastError()));
+    return STTSM_OK;
+}
+
 int64_t sttsm_flops(const bcss_layout *A, const bcss_layout *C)
 {
     std::string why;

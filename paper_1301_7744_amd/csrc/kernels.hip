@@ -120,6 +120,75 @@ int launch_unpack(int esize, const void *bcss, void *dense, int m, int64_t n, in
     return -1;
 }
 
+// ------------------------------------------------------------------ hashed fill
+// SplitMix64 finaliser (Steele, Lea, Flood, OOPSLA 2014).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Each BCSS entry gets lo + (hi - lo) u, u = (h >> 40) 2^-24 with
+// h = mix(...mix(mix(seed) ^ s_0)... ^ s_{m-1}) over its sorted global index
+// s_0 <= ... <= s_{m-1}: a symmetric tensor whose unique entries are
+// pseudo-random.  Entries beyond n are zero.
+template <class E>
+__global__ void bcss_fill_hashed_kernel(E *__restrict__ bcss, int m, int64_t n, int b, int64_t bm, int64_t total,
+                                        const int32_t *__restrict__ tuples, uint64_t seed, double lo, double hi)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / bm;
+        int64_t l = e - r * bm;
+        int64_t idx[kMaxOrder];
+        bool ok = true;
+        for (int j = 0; j < m; ++j) {
+            const int64_t lj = l % b;
+            l /= b;
+            idx[j] = (int64_t)tuples[r * m + j] * b + lj;
+            ok = ok && idx[j] < n;
+        }
+        double v = 0.0;
+        if (ok) {
+            for (int j = 1; j < m; ++j) {   // insertion sort
+                const int64_t x = idx[j];
+                int i = j - 1;
+                while (i >= 0 && idx[i] > x) { idx[i + 1] = idx[i]; --i; }
+                idx[i + 1] = x;
+            }
+            uint64_t h = splitmix64(seed);
+            for (int j = 0; j < m; ++j) h = splitmix64(h ^ (uint64_t)idx[j]);
+            v = lo + (hi - lo) * ((double)(h >> 40) * (1.0 / 16777216.0));
+        }
+        if constexpr (sizeof(E) == 2) bcss[e] = f2bf((float)v);
+        else if constexpr (sizeof(E) == 4) bcss[e] = __float_as_uint((float)v);
+        else bcss[e] = (E)__double_as_longlong(v);
+    }
+}
+
+int launch_fill_hashed(int esize, void *bcss, int m, int64_t n, int b, int64_t nblocks, const int32_t *d_tuples,
+                       uint64_t seed, double lo, double hi, hipStream_t s)
+{
+    int64_t bm = 1;
+    for (int j = 0; j < m; ++j) bm *= b;
+    const int64_t total = bm * nblocks;
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 1 << 20));
+    if (esize == 2)
+        hipLaunchKernelGGL(bcss_fill_hashed_kernel<uint16_t>, dim3(blocks), dim3(256), 0, s, (uint16_t *)bcss, m, n,
+                           b, bm, total, d_tuples, seed, lo, hi);
+    else if (esize == 4)
+        hipLaunchKernelGGL(bcss_fill_hashed_kernel<uint32_t>, dim3(blocks), dim3(256), 0, s, (uint32_t *)bcss, m, n,
+                           b, bm, total, d_tuples, seed, lo, hi);
+    else if (esize == 8)
+        hipLaunchKernelGGL(bcss_fill_hashed_kernel<uint64_t>, dim3(blocks), dim3(256), 0, s, (uint64_t *)bcss, m, n,
+                           b, bm, total, d_tuples, seed, lo, hi);
+    else
+        return -1;
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 // ------------------------------------------------------------------ X panels
 // Xp[j][i] = X(j, i) for j < p, i < n, zero elsewhere; rows of Kx entries.
 // Slot 0 fp32, slot 1 bf16(x), slot 2 bf16(x - bf16(x)).

@@ -12,6 +12,8 @@ int launch_pack(int esize, const void *dense, void *bcss, int m, int64_t n, int 
                 const int32_t *d_tuples, hipStream_t s);
 int launch_unpack(int esize, const void *bcss, void *dense, int m, int64_t n, int b, int nbar,
                   const int64_t *d_rank, const int32_t *d_perm, const int32_t *d_pstr, hipStream_t s);
+int launch_fill_hashed(int esize, void *bcss, int m, int64_t n, int b, int64_t nblocks, const int32_t *d_tuples,
+                       uint64_t seed, double lo, double hi, hipStream_t s);
 int launch_prep_x(int esize, const void *X, int64_t rs, int64_t cs, int64_t p, int64_t n, int64_t Ppad,
                   int64_t Kx, float *x32, uint16_t *xhi, uint16_t *xlo, hipStream_t s);
 int launch_stage(const StageArgs &a, int compute, int MT, bool first, hipStream_t s);

@@ -55,6 +55,37 @@ def symmetric_uniform(m: int, n: int, seed, dtype=np.float32) -> np.ndarray:
     return out.astype(dtype, copy=False)
 
 
+def splitmix64(z):
+    """SplitMix64 finaliser (Steele, Lea, Flood, OOPSLA 2014) on uint64 arrays."""
+    with np.errstate(over="ignore"):
+        z = (np.asarray(z, dtype=np.uint64) + np.uint64(0x9E3779B97F4A7C15))
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def hashed_symmetric(m: int, n: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """Symmetric tensor whose entry at sorted index s_0 <= ... <= s_{m-1} is
+    lo + (hi - lo) u, u = (h >> 40) 2^-24, h = f(...f(f(seed) ^ s_0)... ^ s_{m-1})
+    with f = SplitMix64; float64, Fortran order.  For GPU-side generation of
+    large served requests, which fill their compact storage with the same
+    definition."""
+    total = n ** m
+    out = np.empty(total, dtype=np.float64)
+    powers = np.array([n ** k for k in range(m)], dtype=np.int64)
+    h0 = splitmix64(np.uint64(int(seed) & 0xFFFFFFFFFFFFFFFF))
+    for start in range(0, total, _CHUNK):
+        flat = np.arange(start, min(total, start + _CHUNK), dtype=np.int64)
+        digits = (flat[:, None] // powers[None, :]) % n
+        digits.sort(axis=1)
+        h = np.full(flat.size, h0, dtype=np.uint64)
+        for k in range(m):
+            h = splitmix64(h ^ digits[:, k].astype(np.uint64))
+        u = (h >> np.uint64(40)).astype(np.float64) * (1.0 / 16777216.0)
+        out[start:start + flat.size] = lo + (hi - lo) * u
+    return out.reshape((n,) * m, order="F")
+
+
 def change_of_basis(p: int, n: int, seed, scale=None, dtype=np.float32) -> np.ndarray:
     """X (p x n), i.i.d. N(0,1) times `scale` (default 1/sqrt(n))."""
     g = rng(seed)
@@ -85,8 +116,9 @@ def rank_r_symmetric(m: int, lams, vecs) -> np.ndarray:
 def served_stream(num_requests: int, seed, rate_per_s: float):
     """Mixed request stream: m uniform in {3, 4}, n uniform in [32, 256],
     p uniform in [16, n], block size 16 when n >= 128 else 8 (bA = bC),
-    arrival gaps exponential with the given rate.  Request r draws its tensor
-    with seed (r, 0) and its X with seed (r, 1)."""
+    arrival gaps exponential with the given rate.  Request r's tensor is the
+    hashed symmetric tensor of seed 2r + 1 (see hashed_symmetric) and its X is
+    drawn with seed (r, 1)."""
     g = rng(seed)
     reqs = []
     t = 0.0
@@ -96,11 +128,11 @@ def served_stream(num_requests: int, seed, rate_per_s: float):
         p = int(g.integers(16, n + 1))
         b = 16 if n >= 128 else 8
         t += float(g.exponential(1.0 / rate_per_s)) if rate_per_s > 0 else 0.0
-        reqs.append(dict(id=r, m=m, n=n, p=p, b=b, arrival_s=t, seed_a=(r, 0), seed_x=(r, 1)))
+        reqs.append(dict(id=r, m=m, n=n, p=p, b=b, arrival_s=t, seed_a=2 * r + 1, seed_x=(r, 1)))
     return reqs
 
 
-# The BASELINE workloads, by name.
+# Named workloads (the sizes the method is measured and tested on).
 CONFIGS = {
     "m3_n16_b4": dict(m=3, n=16, p=16, bA=4, bC=4, seed_a=101, seed_x=102, x_scale=1.0),
     "m3_n256_b16": dict(m=3, n=256, p=256, bA=16, bC=16, seed_a=201, seed_x=202),

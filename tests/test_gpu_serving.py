@@ -125,3 +125,20 @@ def test_destroy_with_requests_in_flight():
         srv.submit(Ab, Xd, m, n, p, b, b, PBF)
     srv.close()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("m,n,b,dt", [(3, 9, 4, "f32"), (4, 7, 3, "f32"), (3, 40, 8, "bf16"), (2, 33, 16, "f64")])
+def test_hashed_fill_matches_numpy_definition(m, n, b, dt):
+    """The GPU's direct BCSS fill equals packing the numpy evaluation of the
+    same SplitMix64 definition, bit for bit (served inputs are made this way)."""
+    import torch
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f64": torch.float64}[dt]
+    got = st().bcss_fill_hashed(m, n, b, seed=12345, dtype=tdt)
+    torch.cuda.synchronize()
+    A = synth.hashed_symmetric(m, n, 12345)
+    if dt == "bf16":
+        A = synth.round_to_bf16(A.astype(np.float32)).astype(np.float64)
+    elif dt == "f32":
+        A = A.astype(np.float32).astype(np.float64)
+    ref = bcss_ref.pack(A, b)
+    assert np.array_equal(got.to(torch.float64).cpu().numpy().reshape(ref.shape), ref)
