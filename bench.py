@@ -42,6 +42,23 @@ def measured_traffic(workload, prec, level):
         return None
 
 
+def level_bytes(m, n, p, bA, bC, prec, d):
+    """Algorithmic HBM bytes of loop level d: its input tensor (A in BCSS, or
+    the stored temporary T^(k+1)), the X panel, and its output (T^(k), or C
+    in BCSS), each read or written once."""
+    from math import comb
+    nbar, pbar = -(-n // bA), -(-p // bC)
+    k = m - 1 - d
+    tbytes = 2 if prec in ("bf16", "bf16x3_bf16") else 4
+    in_bytes = 2 if prec == "bf16" else 4
+
+    def temp_elems(kk):   # T^(kk): sorted C-block tuples of length m-kk x sorted prefixes of length kk
+        return comb(pbar + m - kk - 1, m - kk) * comb(nbar + kk - 1, kk) * bA ** kk * bC ** (m - kk)
+    rd = comb(nbar + m - 1, m) * bA ** m * in_bytes if d == 0 else temp_elems(k + 1) * tbytes
+    wr = comb(pbar + m - 1, m) * bC ** m * 4 if k == 0 else temp_elems(k) * tbytes
+    return rd + p * n * (2 if prec == "bf16" else 4) + wr
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,6 +67,7 @@ def parse():
     ap.add_argument("--prec", default="fp32")
     ap.add_argument("--workload", default="m3_n256_b16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum oracle time for the CPU baseline")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before timing, copy this many MiB device to device once (a plain copy kernel of known "
@@ -220,14 +238,19 @@ def main():
 
     log("bench: generating inputs", args.workload)
     A_np, X_np = synth.make_config_inputs(args.workload)
-    A_dense = torch.from_numpy(np.ascontiguousarray(A_np.ravel(order="F"))).to(dev)
-    X = torch.from_numpy(np.ascontiguousarray(X_np)).to(dev)
+    if args.prec == "bf16":
+        # the bf16 form takes bf16 inputs; the oracle sees the same values
+        A_np, X_np = synth.round_to_bf16(A_np), synth.round_to_bf16(X_np)
+    tdt = torch.bfloat16 if args.prec == "bf16" else torch.float32
+    A_dense = torch.from_numpy(np.ascontiguousarray(A_np.ravel(order="F"))).to(tdt).to(dev)
+    X = torch.from_numpy(np.ascontiguousarray(X_np)).to(tdt).to(dev)
     A = st.bcss_pack(A_dense, m, n, bA)
     del A_dense
     C, ws = st.sttsm(A, X, m, n, p, bA, bC, prec)
     torch.cuda.synchronize()
     flops = st.sttsm_flops(m, n, p, bA, bC)
-    levels = [st.sttsm_plan_info(m, n, p, bA, bC, prec, d) for d in range(m)]
+    levels = [st.sttsm_plan_info(m, n, p, bA, bC, prec, d, dtype=st.BF16 if args.prec == "bf16" else st.F32)
+              for d in range(m)]
     stream = torch.cuda.current_stream()
 
     log("bench: warmup", args.warmup)
@@ -235,29 +258,79 @@ def main():
         st.sttsm(A, X, m, n, p, bA, bC, prec, C=C, ws=ws)
     torch.cuda.synchronize()
 
-    # Timed region: K steps, synchronised on both sides; per-level kernel
-    # times from HIP events recorded on the launch stream.
+    # Timed region 1 (the reported throughput): K steps, each one replay of
+    # a HIP graph holding one whole sttsm call (X panels and every level's
+    # kernel), synchronised on both sides.  The graph removes the host's
+    # per-launch cost between the kernels; every replay does all the work.
+    graph = None
+    if not args.eager:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            st.sttsm(A, X, m, n, p, bA, bC, prec, C=C, ws=ws)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            st.sttsm(A, X, m, n, p, bA, bC, prec, C=C, ws=ws)
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+
+    def timed(step):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps, (time.perf_counter() - t) * 1e3 / args.steps
+
+    eager_step = lambda: st.sttsm(A, X, m, n, p, bA, bC, prec, C=C, ws=ws)
+    C_graph = None
+    if graph is not None:
+        ms_step, wall_ms = timed(graph.replay)
+        C_graph = C.clone()
+    # Timed region 2: the same K steps launched eagerly, with HIP events
+    # recorded on the launch stream around each level's kernel (per-level
+    # kernel times for the roofline).
     st.profile_enable(max(16, args.steps * m + 8))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
-        st.sttsm(A, X, m, n, p, bA, bC, prec, C=C, ws=ws)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    eager_ms, eager_wall = timed(eager_step)
     prof = st.profile_read(8)
     st.profile_disable()
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    log("bench: %.4f ms/step (wall %.4f ms/step)" % (ms_step, wall * 1e3 / args.steps))
+    if graph is None:
+        ms_step, wall_ms = eager_ms, eager_wall
+    else:
+        torch.cuda.synchronize()
+        if not torch.equal(C_graph, C):
+            raise RuntimeError("graph replay and eager launches gave different C")
+    log("bench: %.4f ms/step (%s; wall %.4f ms/step), eager %.4f ms/step" %
+        (ms_step, "graph replay" if graph is not None else "eager", wall_ms, eager_ms))
     gflops = flops / (ms_step * 1e-3) / 1e9
 
-    # Dominant kernel: the level with the largest flop count (the first on ties).
+    # Dominant kernel: the level with the largest flop count (the first on
+    # ties); its roofline is MFMA or HBM, whichever bounds it by the model
+    # time = max(flops / MFMA peak, algorithmic bytes / HBM peak).
     dom = max(range(m), key=lambda d: (levels[d]["flops"], -d))
     dom_ms = prof[dom][0] / prof[dom][1]
-    achieved = levels[dom]["flops"] / (dom_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.prec]
+    dom_bytes = level_bytes(m, n, p, bA, bC, args.prec, dom)
+    t_mfma = levels[dom]["flops"] / (peak * 1e12)
+    t_hbm = dom_bytes / (PEAK_HBM_GBS * 1e9)
+    if t_mfma >= t_hbm:
+        roof = {"bound": "mfma", "achieved": round(levels[dom]["flops"] / (dom_ms * 1e-3) / 1e12, 3), "peak": peak,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": round(dom_bytes / (dom_ms * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["traffic"] = measured_traffic(args.workload, args.prec, dom)
+    roof["kernel"] = "level %d (%.3f GFLOP, %.1f MB algorithmic per launch)" % (dom, levels[dom]["flops"] / 1e9,
+                                                                                 dom_bytes / 1e6)
+    roof["kernel_us"] = round(dom_ms * 1e3, 3)
     level_times = {str(d): round(prof[d][0] / prof[d][1] * 1e3, 3) for d in range(m) if d in prof}
 
     # Accuracy of this run against the FP64 oracle (also the CPU baseline).
@@ -276,12 +349,10 @@ def main():
         "data": "synthetic (seeded; symmetric A uniform[-1,1] mirrored from sorted-index entries, X N(0,1)/sqrt(n))",
         "config": {"workload": args.workload, "m": m, "n": n, "p": p, "bA": bA, "bC": bC, "prec": args.prec,
                    "flops_per_step": flops, "mfma_roofline_frac": round(gflops / (peak * 1e3), 4),
+                   "launch": "graph replay" if graph is not None else "eager",
+                   "eager_ms_per_step": round(eager_ms, 5),
                    "level_us": level_times},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4),
-                     "traffic": measured_traffic(args.workload, args.prec, dom),
-                     "kernel": "stage_kernel level %d (%d GFLOP/launch)" % (dom, levels[dom]["flops"] // 10 ** 9),
-                     "kernel_us": round(dom_ms * 1e3, 3)},
+        "roofline": roof,
     }
 
     if not args.no_cpu_baseline:

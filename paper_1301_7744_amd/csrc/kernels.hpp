@@ -1,4 +1,4 @@
-// Launchers of the gfx950 kernels (defined in kernels.hip).  Each returns 0,
+// Launchers of the gfx950 kernels (defined in kernels.hip and stage_bf16.hip).  Each returns 0,
 // or -1 when the launch could not be made.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -24,6 +24,15 @@ int launch_grouped(int compute, const StageArgs *d_stages, const GroupedTask *d_
                    int grid, hipStream_t s);
 // Whether the block-copy kernel is instantiated for order m and nbar blocks.
 bool fast_supported(int m, int nbar);
+// Block-copy bf16 stage kernel (stage_bf16.hip): supported shapes, its tile,
+// the per-level launch, and the grouped persistent launch over tasks whose
+// stages all share (m, b, k).
+bool bf16_fast_supported(int m, int bA, int bC, int nbar);
+void bf16_fast_tile(int b, int *MT, int *NT, int *KT, int *PD);   // the default tile
+bool bf16_tile_supported(int b, int NT, int KT, int PD);
+int launch_stage_bf16(const StageArgs &a, int NT, int KT, int PD, hipStream_t s);
+int launch_grouped_bf16(int m, int b, int k, const StageArgs *d_stages, const GroupedTask *d_tasks, int ntasks,
+                        int *d_head, int grid, hipStream_t s);
 int launch_prep_xt(int esize, const void *X, int64_t rs, int64_t cs, int64_t p, int64_t n, int64_t Kt, int64_t Pt,
                    float *xt, hipStream_t s);
 

@@ -126,6 +126,25 @@ static bool fast_tile_override(int level, int *mt, int *nt, int *kt, int *pd)
     return sscanf(p.c_str(), "%dx%dx%dx%d", mt, nt, kt, pd) == 4;
 }
 
+// Measurement override of the bf16 block-copy tiles: STTSM_BF16_TILE =
+// "NTxKTxPD" for every level, or a comma-separated list per level.
+static bool bf16_tile_override(int level, int *nt, int *kt, int *pd)
+{
+    const char *e = getenv("STTSM_BF16_TILE");
+    if (!e || !*e) return false;
+    std::string str(e);
+    std::vector<std::string> parts;
+    size_t pos = 0;
+    while (pos <= str.size()) {
+        size_t c = str.find(',', pos);
+        if (c == std::string::npos) c = str.size();
+        parts.push_back(str.substr(pos, c - pos));
+        pos = c + 1;
+    }
+    const std::string &p = parts.size() == 1 ? parts[0] : (level < (int)parts.size() ? parts[level] : std::string());
+    return sscanf(p.c_str(), "%dx%dx%d", nt, kt, pd) == 3;
+}
+
 static int kt_of(int compute) { return compute == CMP_FP32 ? 16 : 32; }
 
 bool plan_build_host(const PlanKey &key, Plan *P, std::string *err)
@@ -189,6 +208,17 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err)
         const int in_dt = d == 0 ? key.in_dtype : tdt[k + 1];
         fast[d] = cmp[d] == CMP_FP32 && in_dt == F32 && mblk == 256 && (bA == 4 || bA == 8 || bA == 16) &&
                   bC % 4 == 0 && !key.generic_only && !key.grouped && fast_supported(m, nbar);
+    }
+    // Levels that take the block-copy bf16 kernel: bf16 operands stored bf16,
+    // square blocks of 8 or 16, order 3 or 4; the output is the bf16
+    // temporary, or C in fp32 at the last level.
+    bool fast16[kMaxOrder];
+    for (int d = 0; d < m; ++d) {
+        const int k = m - 1 - d;
+        const int in_dt = d == 0 ? key.in_dtype : tdt[k + 1];
+        const int out_dt = k == 0 ? F32 : tdt[k];
+        fast16[d] = cmp[d] == CMP_BF16 && in_dt == BF16 && out_dt == (k == 0 ? F32 : BF16) &&
+                    bf16_fast_supported(m, bA, bC, nbar) && !key.generic_only;
     }
 
     // Workspace: X panels first.
@@ -312,6 +342,15 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err)
         a.osk = (int32_t)os[k];
         S.tile = key.grouped ? TileCfg{kGroupedMT, kGroupedNT, 2, 2} : choose_tile(Mblk);
         S.fast = fast[d];
+        S.fast_bf16 = fast16[d];
+        if (S.fast_bf16) {
+            int tmt, tnt, tkt, tpd;
+            bf16_fast_tile(bA, &tmt, &tnt, &tkt, &tpd);
+            S.tile = TileCfg{tmt, tnt, 0, 0, tkt, tpd};
+            int ont, okt, opd;
+            if (!key.grouped && bf16_tile_override(d, &ont, &okt, &opd) && bf16_tile_supported(bA, ont, okt, opd))
+                S.tile = TileCfg{tmt, ont, 0, 0, okt, opd};
+        }
         for (int j = 0; j < m; ++j) {
             a.ext_in[j] = ext_in[j];
             a.gs[j] = (int32_t)gs[j];

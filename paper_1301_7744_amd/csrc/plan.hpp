@@ -31,6 +31,7 @@ struct StagePlan {
     int k = 0;          // contracted mode
     int compute = CMP_FP32;
     bool fast = false;  // block-copy staging kernel (whole 256-row blocks, bA | 16)
+    bool fast_bf16 = false;   // block-copy bf16 kernel (m in {3, 4}, bA = bC in {8, 16})
     TileCfg tile{};
     StageArgs args{};   // everything but in/out/xp pointers
     std::vector<GroupDesc> groups;

@@ -5,7 +5,7 @@
 // cap allows, (2) stages the inputs and index tables of newly admitted
 // requests into their arena regions and builds their padded X panels, and
 // (3) runs the next level of every active request in grouped persistent
-// launches (one per compute form present) whose workgroups take tiles of all
+// launches (one per kernel class present) whose workgroups take tiles of all
 // requests from one shared queue.  Completion of the last level marks a
 // request done; its A, X, temporaries and tables are released at once and
 // its C when the caller fetches it.
@@ -29,6 +29,15 @@
 using namespace symt;
 
 namespace {
+
+// Kernel class of a stage in a server round: the compute form (generic
+// grouped kernel), or one (m, b, k) of the block-copy bf16 kernel.
+constexpr int kLaunchClasses = CMP_X3 + 1 + 2 * 2 * 4;
+int launch_class(int m, int b, const StagePlan &St)
+{
+    if (!St.fast_bf16) return St.compute;
+    return CMP_X3 + 1 + ((m - 3) * 2 + (b == 16 ? 1 : 0)) * 4 + St.k;
+}
 
 size_t round256(size_t x) { return (x + 255) / 256 * 256; }
 
@@ -339,41 +348,46 @@ void worker_loop(sttsm_server *S)
         if (ok) ok = ensure_capacity(S, nst, ntk, &err);
         int nl = 0;
         if (ok) {
+            // One launch per kernel class: the generic grouped kernel per
+            // compute form, and the block-copy bf16 kernel per (m, b, k).
             size_t ti = 0;
-            for (int cmp = CMP_FP32; cmp <= CMP_X3 && ok; ++cmp) {
-                const size_t t0 = ti;
+            size_t cls_t0[kLaunchClasses] = {}, cls_cnt[kLaunchClasses] = {};
+            int cls_m[kLaunchClasses] = {}, cls_b[kLaunchClasses] = {}, cls_k[kLaunchClasses] = {};
+            for (int cls = 0; cls < kLaunchClasses; ++cls) {
+                cls_t0[cls] = ti;
                 for (size_t i = 0; i < active.size(); ++i) {
                     const Req *q = active[i];
                     const StagePlan &St = q->plan->stages[q->level];
-                    if (St.compute != cmp) continue;
+                    if (launch_class(q->plan->m, q->plan->bA, St) != cls) continue;
                     S->h_stages[i] = stage_args_for(q, q->level);
                     for (const Task &t : St.tasks) S->h_tasks[ti++] = GroupedTask{(int32_t)i, t.group, t.mt, t.nt};
+                    cls_m[cls] = q->plan->m;
+                    cls_b[cls] = q->plan->bA;
+                    cls_k[cls] = St.k;
                 }
-                if (ti == t0) continue;
-                // stage args for this launch were written above; copy once below
-                (void)t0;
+                cls_cnt[cls] = ti - cls_t0[cls];
             }
             if (hipMemcpyAsync(S->d_stages, S->h_stages, nst * sizeof(StageArgs), hipMemcpyHostToDevice, S->stream) !=
                     hipSuccess ||
                 hipMemcpyAsync(S->d_tasks, S->h_tasks, ntk * sizeof(GroupedTask), hipMemcpyHostToDevice, S->stream) !=
                     hipSuccess ||
-                hipMemsetAsync(S->d_heads, 0, 3 * sizeof(int), S->stream) != hipSuccess) {
+                hipMemsetAsync(S->d_heads, 0, kLaunchClasses * sizeof(int), S->stream) != hipSuccess) {
                 ok = false;
                 err = "server: upload of the round failed";
             }
-            // launch one grouped kernel per compute form, over its task range
-            size_t t0 = 0;
-            for (int cmp = CMP_FP32; cmp <= CMP_X3 && ok; ++cmp) {
-                size_t cnt = 0;
-                for (const Req *q : active)
-                    if (q->plan->stages[q->level].compute == cmp) cnt += q->plan->stages[q->level].tasks.size();
-                if (!cnt) continue;
-                if (launch_grouped(cmp, S->d_stages, S->d_tasks + t0, (int)cnt, S->d_heads + cmp, S->grid,
-                                   S->stream)) {
+            for (int cls = 0; cls < kLaunchClasses && ok; ++cls) {
+                if (!cls_cnt[cls]) continue;
+                const int cnt = (int)cls_cnt[cls];
+                const GroupedTask *tk = S->d_tasks + cls_t0[cls];
+                int *head = S->d_heads + cls;
+                const int rc = cls < CMP_X3 + 1
+                                   ? launch_grouped(cls, S->d_stages, tk, cnt, head, S->grid, S->stream)
+                                   : launch_grouped_bf16(cls_m[cls], cls_b[cls], cls_k[cls], S->d_stages, tk, cnt,
+                                                         head, S->grid, S->stream);
+                if (rc) {
                     ok = false;
                     err = "server: grouped launch failed";
                 }
-                t0 += cnt;
                 ++nl;
             }
         }
@@ -445,7 +459,7 @@ int sttsm_server_create(void *arena, size_t arena_bytes, int32_t max_inflight, s
     if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess)
         return fail(STTSM_EHIP, "hipStreamCreate failed");
     if (hipEventCreateWithFlags(&S->ev, hipEventDisableTiming) != hipSuccess ||
-        hipMalloc((void **)&S->d_heads, 4 * sizeof(int)) != hipSuccess) {
+        hipMalloc((void **)&S->d_heads, kLaunchClasses * sizeof(int)) != hipSuccess) {
         (void)hipStreamDestroy(S->stream);
         return fail(STTSM_EHIP, "server: cannot create event or queue heads");
     }

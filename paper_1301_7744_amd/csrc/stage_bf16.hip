@@ -1,0 +1,548 @@
+// Block-copy bf16 stage kernel for gfx950: one level of the algorithm-by-blocks
+// (Fig. mD) with bf16 operands, fp32 MFMA accumulation
+// (v_mfma_f32_32x32x16_bf16), for order M in {3, 4} and square blocks of
+// B in {8, 16} entries per mode (bA = bC = B).
+//
+// Tile contract (the same as the other stage kernels): one workgroup of four
+// waves computes an MT x NT tile of one row group's GEMM
+//   Out[row][nn] = sum_kk In[row][kk] * X[nn][kk],
+// rows = entries of an input block without the contracted mode K,
+// kk = ibar*B + lk over the contracted mode, nn over the group's output
+// columns.  Here a tile's rows are the two lowest non-contracted modes in
+// full (MT = B*B); the remaining non-contracted modes are fixed per M tile.
+//
+// Staging: every input block is read from HBM as contiguous 16-byte vectors
+// in its stored order (coalesced for every permutation) and written to LDS in
+// one canonical layout.  Which logical mode sits at which stored position is
+// fixed by the block's insertion position Q (the permutation of §5.3 / App. B)
+// and is a compile-time case here: the kernel switches once per block on Q,
+// uniformly across the wave, so each case's address arithmetic is shifts and
+// adds on constants.  For levels below the last (K > 0) LDS holds [kk][row]
+// (row fastest) and the MFMA operands are read with ds_read_b64_tr_b16, which
+// transposes 4x4 groups of 16-bit entries on the way out; at the last level
+// (K = 0, where mode 0 is always the contracted one) LDS holds [row][kk] and
+// operands are plain 16-byte reads.  X comes from the zero-padded bf16 panel
+// [Ppad][Kx] into LDS [nn][kk].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace symt {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16;
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// Two fp32 -> bf16, round to nearest, ties to even (v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint32_t to_bf16x2(float a, float b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2{a, b}), bf16x2));
+}
+
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// Stored position of logical mode l inside an input block whose contracted
+// mode K was inserted at position Q (modes 0..K are the sorted ones).
+constexpr int stored_pos(int l, int K, int Q)
+{
+    return l == K ? Q : (l > K ? l : (l < Q ? l : l + 1));
+}
+// j-th non-contracted logical mode.
+constexpr int mmode_of(int j, int K) { return j < K ? j : j + 1; }
+
+constexpr int kBf16MaxBlocks = 512;   // input blocks per group the LDS table holds
+
+template <int M, int B, int K, int NT, int KT>
+struct Bf16Cfg {
+    static constexpr int MT = B * B;
+    static constexpr bool KM = K == 0;                  // LDS [row][kk] (else [kk][row])
+    static constexpr int RS = MT + 16;                  // [kk][row] row stride (bf16)
+    static constexpr int RSK = KT + 8;                  // [row][kk] row stride
+    static constexpr int XS = KT + 8;                   // X [nn][kk] row stride
+    static constexpr int IN_ELEMS = KM ? MT * RSK : KT * RS;
+    static constexpr int WM = MT >= 128 ? 2 : 1, WN = 4 / WM;
+    static constexpr int WTM = MT / WM, WTN = NT / WN;
+    static constexpr int TM = WTM / 32, TN = WTN / 32;
+    static constexpr int G = KT / B;                    // whole blocks per K chunk
+    static constexpr int PART = B * B * B / 8;          // 16-byte vectors of one block's tile part
+    static constexpr int VEC = G * PART;                // ... per chunk
+    static constexpr int NV = (VEC + 255) / 256;        // per thread
+    static constexpr int XV = NT * KT / 8;              // X vectors per chunk
+    static constexpr int NXV = (XV + 255) / 256;
+    static_assert(KT % B == 0 && KT % 16 == 0, "chunk");
+    static_assert(TM >= 1 && TN >= 1, "tile");
+    static_assert(PART % 64 == 0, "a block part spans whole waves");
+};
+
+constexpr int kOutRow = 40;   // row stride (bf16) of a wave's 32 x 32 output staging tile
+
+template <int M, int B, int K, int NT, int KT>
+struct Bf16Smem {
+    using C = Bf16Cfg<M, B, K, NT, KT>;
+    union {
+        struct {
+            __attribute__((aligned(16))) u16 s_in[2][C::IN_ELEMS];
+            __attribute__((aligned(16))) u16 s_x[2][NT * C::XS];
+        };
+        // epilogue: one 32 x 32 output subtile per wave, [nn][mm]
+        __attribute__((aligned(16))) u16 s_out[4][32 * kOutRow];
+    };
+    int64_t s_ioff[kBf16MaxBlocks];
+    int32_t s_iq[kBf16MaxBlocks];
+};
+
+// Where a thread's vector lands, for one insertion position Q: element offset
+// inside the stored block (goff), LDS offset (loff) in the chunk buffer, and
+// whether its 8 entries run along the contracted mode (transposed write into
+// a [kk][row] buffer).  d0, d1, d2 are the vector's digits at the three
+// stored positions the tile part spans in full (ascending; d0 counts entries,
+// a multiple of 8); fixed_digits are the digits of the non-contracted modes
+// beyond the first two, fixed by the M tile.
+template <int M, int B, int K, int Q, int RS, int RSK, bool KM>
+__device__ __forceinline__ void place(int d0, int d1, int d2, const int *fixed_digits, int kbase, int *goff,
+                                      int *loff, bool *along_k)
+{
+    constexpr int m0 = mmode_of(0, K), m1 = mmode_of(1, K);
+    constexpr int pk = stored_pos(K, K, Q), p0 = stored_pos(m0, K, Q), p1 = stored_pos(m1, K, Q);
+    // The three full positions in ascending order.
+    constexpr int lo = pk < p0 ? (pk < p1 ? pk : p1) : (p0 < p1 ? p0 : p1);
+    constexpr int hi = pk > p0 ? (pk > p1 ? pk : p1) : (p0 > p1 ? p0 : p1);
+    constexpr int mid = pk + p0 + p1 - lo - hi;
+    static_assert(lo == 0, "stored position 0 is always spanned in full");
+    int g = d0 + d1 * ipow(B, mid) + d2 * ipow(B, hi);
+#pragma unroll
+    for (int j = 2; j < M - 1; ++j) {
+        const int p = stored_pos(mmode_of(j, K), K, Q);
+        g += fixed_digits[j - 2] * ipow(B, p);
+    }
+    *goff = g;
+    // Digits per logical role.
+    auto digit_at = [&](int pos) { return pos == 0 ? d0 : (pos == mid ? d1 : d2); };
+    const int dk = digit_at(pk), r0 = digit_at(p0), r1 = digit_at(p1);
+    const int row = r0 + B * r1;
+    if constexpr (KM) *loff = row * RSK + kbase + dk;
+    else *loff = (kbase + dk) * RS + row;
+    *along_k = pk == 0;
+}
+
+template <int M, int B, int K, int NT, int KT, int PD>
+__device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, Bf16Smem<M, B, K, NT, KT> &sm)
+{
+    using C = Bf16Cfg<M, B, K, NT, KT>;
+    constexpr int RS = C::RS, RSK = C::RSK, XS = C::XS;
+    constexpr int WM = C::WM, WTM = C::WTM, WTN = C::WTN, TM = C::TM, TN = C::TN;
+    constexpr int G = C::G, PART = C::PART, NV = C::NV, NXV = C::NXV, XV = C::XV;
+    constexpr bool B_IS_IN = K != 0;   // output rows run along the block rows unless mode 0 is contracted
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const GroupDesc gd = a.groups[task.group];
+    const int n0 = task.nt * NT;
+    const int Nvalid = gd.jcount * B;
+    const int nbar = a.nbar;
+    const int nch = (nbar + G - 1) / G;
+    const u16 *in = (const u16 *)a.in;
+    const u16 *xp = (const u16 *)a.xp;
+    const int64_t Kx = a.Kx, Kpad = a.Kpad, Ppad = a.Ppad;
+
+    // Digits of the fixed non-contracted modes of this M tile.
+    int fixed[M > 3 ? M - 3 : 1];
+    {
+        int r = task.mt;
+#pragma unroll
+        for (int j = 0; j < M - 3; ++j) {
+            fixed[j] = r % B;
+            r /= B;
+        }
+    }
+    for (int i = tid; i < nbar; i += 256) {
+        const InEntry ie = a.in_tab[gd.in_row + i];
+        sm.s_ioff[i] = ie.off;
+        sm.s_iq[i] = ie.q;
+    }
+    // This thread's vectors: block g of the chunk and digits in the part.
+    // Threads beyond the chunk's vector count (only when it is not a
+    // multiple of 256) load a duplicate of the last vector and store nothing,
+    // so that every load is unconditional: the compiler can then wait for
+    // exactly the oldest register stage instead of every load in flight.
+    int vg[NV], vd0[NV], vd1[NV], vd2[NV];
+    bool vok[NV];
+#pragma unroll
+    for (int f = 0; f < NV; ++f) {
+        const int v0 = tid + 256 * f;
+        vok[f] = C::VEC % 256 == 0 || v0 < C::VEC;
+        const int v = vok[f] ? v0 : C::VEC - 1;
+        vg[f] = v / PART;
+        const int w = v % PART;
+        vd0[f] = 8 * (w % (B / 8));
+        const int w1 = w / (B / 8);
+        vd1[f] = w1 % B;
+        vd2[f] = w1 / B;
+    }
+    __syncthreads();
+
+    // PD register stages of global loads: chunk c lives in stage c % PD
+    // from its load until its store to LDS.
+    u32x4 rin[PD][NV], rx[PD][NXV];
+    int rl[PD][NV];
+    bool rk[PD][NV], rv[PD][NV], rxv[PD][NXV];
+    auto load_chunk = [&](int c, int u) {
+#pragma unroll
+        for (int f = 0; f < NV; ++f) {
+            const int ib = c * G + vg[f];
+            // ib is uniform across the wave (a block part spans whole
+            // waves); a block beyond nbar is read as block 0 and stored as
+            // zeros in block 0's layout, which covers the same LDS entries
+            const bool valid = ib < nbar;
+            const int ibc = valid ? ib : 0;
+            const int q = __builtin_amdgcn_readfirstlane(sm.s_iq[ibc]);
+            int goff = 0, loff = 0;
+            bool ak = false;
+            const int kb = vg[f] * B;
+            switch (q) {
+#define STTSM_Q(QQ) \
+    case QQ: \
+        if constexpr (QQ <= K) place<M, B, K, QQ, RS, RSK, C::KM>(vd0[f], vd1[f], vd2[f], fixed, kb, &goff, &loff, &ak); \
+        break;
+                STTSM_Q(0) STTSM_Q(1) STTSM_Q(2) STTSM_Q(3)
+#undef STTSM_Q
+            default: break;
+            }
+            rl[u][f] = loff;
+            rk[u][f] = ak;
+            rv[u][f] = valid;
+            rin[u][f] = *(const u32x4 *)(in + sm.s_ioff[ibc] + goff);
+        }
+#pragma unroll
+        for (int f = 0; f < NXV; ++f) {
+            const int v0 = tid + 256 * f;
+            const int v = XV % 256 == 0 || v0 < XV ? v0 : XV - 1;
+            const int row = v / (KT / 8), kv = (v % (KT / 8)) * 8;
+            const int64_t ng = n0 + row, kg = (int64_t)c * KT + kv;
+            const bool ok = ng < Ppad && kg < Kpad;
+            rxv[u][f] = ok;
+            rx[u][f] = *(const u32x4 *)(xp + (ok ? ng * Kx + kg : 0));
+        }
+    };
+    auto store_chunk = [&](int buf, int u) {
+        u16 *si = sm.s_in[buf];
+        const u32x4 zero = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int f = 0; f < NV; ++f) {
+            if (!vok[f]) continue;
+            const u32x4 w = rv[u][f] ? rin[u][f] : zero;
+            if constexpr (!C::KM) {
+                if (rk[u][f]) {   // 8 entries along kk: one per LDS row
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        si[rl[u][f] + (2 * e) * RS] = (u16)(w[e] & 0xFFFFu);
+                        si[rl[u][f] + (2 * e + 1) * RS] = (u16)(w[e] >> 16);
+                    }
+                    continue;
+                }
+            }
+            *(u32x4 *)&si[rl[u][f]] = w;
+        }
+#pragma unroll
+        for (int f = 0; f < NXV; ++f) {
+            const int v = tid + 256 * f;
+            if (XV % 256 != 0 && v >= XV) continue;
+            const int row = v / (KT / 8), kv = (v % (KT / 8)) * 8;
+            *(u32x4 *)&sm.s_x[buf][row * XS + kv] = rxv[u][f] ? rx[u][f] : zero;
+        }
+    };
+
+    f32x16 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const int r32 = lane & 31, half = lane >> 5;
+    const int grp = lane >> 4, gl = lane & 15;   // 16-lane group, lane inside it
+    const bool wave_live = n0 + wn * WTN < Nvalid;
+
+    // MFMAs of chunk c; after its first k step, the loads of chunk c + PD go
+    // out into the register stage u that chunk c has just left.
+    auto mfma_chunk = [&](int buf, int c, int u) {
+        const u16 *si = sm.s_in[buf];
+        const u16 *sx = sm.s_x[buf];
+#pragma unroll
+        for (int s = 0; s < KT / 16; ++s) {
+            bf16x8 va[TM], vb[TN];
+            if (wave_live) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const int rb = wm * WTM + 32 * i;
+                    if constexpr (C::KM) {
+                        va[i] = __builtin_bit_cast(bf16x8, *(const u16x8 *)&si[(rb + r32) * RSK + 16 * s + 8 * half]);
+                    } else {
+                        // Lane 4t + u of a 16-lane group points at row kk0 + t,
+                        // entries rbase + 4u .. +3; the transposing read hands
+                        // lane i of the group entries (rbase + i, kk0 .. kk0+3).
+                        const int kk0 = 16 * s + 8 * (grp >> 1);
+                        const int rbase = rb + 16 * (grp & 1);
+                        const int o = (kk0 + (gl >> 2)) * RS + rbase + 4 * (gl & 3);
+                        typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+                        const s16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(si + o));
+                        const s16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(si + o + 4 * RS));
+                        va[i] = __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    vb[j] = __builtin_bit_cast(bf16x8,
+                                               *(const u16x8 *)&sx[(wn * WTN + 32 * j + r32) * XS + 16 * s + 8 * half]);
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) {
+                        if constexpr (B_IS_IN)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vb[j], va[i], acc[i][j], 0, 0, 0);
+                        else
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[i], vb[j], acc[i][j], 0, 0, 0);
+                    }
+            }
+            if (s == 0) load_chunk(c + PD, u);
+        }
+    };
+
+    // Every load is issued unconditionally (chunks past the end read valid
+    // addresses and are masked to zero), and the chunk loop runs a multiple
+    // of PD times, so that the loads in flight are the same on every path
+    // and each store waits only for its own stage.  The extra chunks add
+    // zeros.
+    const int nch_pad = (nch + PD - 1) / PD * PD;
+#pragma unroll
+    for (int u = 0; u < PD; ++u) load_chunk(u, u);
+    for (int c0 = 0; c0 < nch_pad; c0 += PD) {
+#pragma unroll
+        for (int u = 0; u < PD; ++u) {
+            const int c = c0 + u;
+            store_chunk(c & 1, u);
+            __syncthreads();
+            mfma_chunk(c & 1, c, u);
+        }
+    }
+
+    // Epilogue.  Output row mm of the tile (digits r0 = mm % B, r1 = mm / B
+    // of the two lowest non-contracted modes, the rest fixed by the M tile)
+    // sits at opart(mm) inside an output block; column ng of the group at
+    // npart(ng) = out_base + (ng / B) out_jstride + (ng % B) osk.
+    int64_t fixed_off = 0;
+#pragma unroll
+    for (int j = 0; j < M - 3; ++j) fixed_off += (int64_t)fixed[j] * a.mos[j + 2];
+    auto opart = [&](int mm) { return (int64_t)(mm % B) * a.mos[0] + (int64_t)(mm / B) * a.mos[1] + fixed_off; };
+    auto npart = [&](int ng) {
+        return gd.out_base + (int64_t)(ng / B) * gd.out_jstride + (int64_t)(ng % B) * a.osk;
+    };
+    // D[r][lane%32] of a 32x32 subtile: register r holds row 8(r/4) + 4(lane/32) + r%4.
+    if constexpr (K == 0) {
+        // C in fp32.  Lanes run along the output columns, whose C-block mode
+        // is mode 0 (stride 1): each store covers 2 x 128 contiguous bytes.
+        if (wave_live) {
+            float *out = (float *)a.out;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int ng = n0 + wn * WTN + j * 32 + r32;
+                if (ng < Nvalid) {
+                    float *oj = out + npart(ng);
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int mm = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                            oj[opart(mm)] = acc[i][j][r];
+                        }
+                }
+            }
+        }
+    } else {
+        // bf16 temporary.  Lanes run along the tile rows (block mode 0,
+        // stride 1); each wave stages one 32 x 32 subtile at a time in LDS as
+        // [column][row] and writes it back as 16-byte row runs.
+        __syncthreads();   // every wave is done with the staging buffers
+        u16 *so = sm.s_out[wave];
+        u16 *out = (u16 *)a.out;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+#pragma unroll
+                for (int r = 0; r < 16; r += 2) {
+                    const uint32_t h = to_bf16x2(acc[i][j][r], acc[i][j][r + 1]);
+                    const int row = 8 * (r >> 2) + 4 * half + (r & 3);
+                    so[row * kOutRow + r32] = (u16)(h & 0xFFFFu);
+                    so[(row + 1) * kOutRow + r32] = (u16)(h >> 16);
+                }
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int v = lane + 64 * h;            // 128 runs of 8 entries
+                    const int col = v >> 2, run = (v & 3) * 8;
+                    const u32x4 w = *(const u32x4 *)&so[col * kOutRow + run];
+                    const int ng = n0 + wn * WTN + j * 32 + col;
+                    const int mm = wm * WTM + i * 32 + run;
+                    if (wave_live && ng < Nvalid) *(u32x4 *)(out + npart(ng) + opart(mm)) = w;
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+    }
+}
+
+template <int M, int B, int K, int NT, int KT, int PD>
+__global__ __launch_bounds__(256, 2) void stage_fast_bf16(const StageArgs a)
+{
+    __shared__ Bf16Smem<M, B, K, NT, KT> sm;
+    bf16_tile<M, B, K, NT, KT, PD>(a, a.tasks[blockIdx.x], sm);
+}
+
+// Grouped persistent form for the server: every task names its stage; all
+// stages of one launch share (M, B, K).  Workgroups pull tasks from one
+// atomic counter until the queue is empty; tasks never wait on each other.
+template <int M, int B, int K, int NT, int KT, int PD>
+__global__ __launch_bounds__(256, 2) void grouped_fast_bf16(const StageArgs *__restrict__ stages,
+                                                            const GroupedTask *__restrict__ tasks, int ntasks,
+                                                            int *__restrict__ queue_head)
+{
+    __shared__ Bf16Smem<M, B, K, NT, KT> sm;
+    __shared__ int s_t;
+    for (;;) {
+        if (threadIdx.x == 0) s_t = atomicAdd(queue_head, 1);
+        __syncthreads();
+        const int t = s_t;
+        __syncthreads();
+        if (t >= ntasks) break;
+        const GroupedTask gt = tasks[t];
+        bf16_tile<M, B, K, NT, KT, PD>(stages[gt.stage], Task{gt.group, gt.mt, gt.nt}, sm);
+        __syncthreads();
+    }
+}
+
+// Default tile (NT, KT, PD) per block size; the grouped kernel always uses it.
+template <int B>
+struct Bf16Default {
+    static constexpr int NT = 128, KT = 32, PD = 1;
+};
+
+// Other per-level tiles (NT, KT, PD), selectable for measurement.
+#define STTSM_BF16_TILES_16(X) X(64, 32, 1) X(64, 32, 2) X(64, 16, 2) X(64, 16, 3) X(128, 16, 2) X(128, 32, 2)
+#define STTSM_BF16_TILES_8(X) X(256, 32, 1) X(128, 32, 2) X(128, 16, 2) X(128, 16, 3)
+
+template <int M, int B, int K>
+int launch_one(const StageArgs &a, int NT, int KT, int PD, const StageArgs *d_stages, const GroupedTask *d_tasks,
+               int ntasks, int *d_head, int grid, hipStream_t s)
+{
+    using D = Bf16Default<B>;
+    if (d_stages) {
+        if (NT != D::NT || KT != D::KT || PD != D::PD) return -1;
+        const dim3 g((unsigned)std::max(1, std::min(grid, ntasks))), b(256);
+        hipLaunchKernelGGL((grouped_fast_bf16<M, B, K, D::NT, D::KT, D::PD>), g, b, 0, s, d_stages, d_tasks, ntasks,
+                           d_head);
+        return 0;
+    }
+    const dim3 g((unsigned)a.ntasks), b(256);
+    if (NT == D::NT && KT == D::KT && PD == D::PD) {
+        hipLaunchKernelGGL((stage_fast_bf16<M, B, K, D::NT, D::KT, D::PD>), g, b, 0, s, a);
+        return 0;
+    }
+#define STTSM_TRY(nt, kt, pd) \
+    if (NT == nt && KT == kt && PD == pd) { \
+        hipLaunchKernelGGL((stage_fast_bf16<M, B, K, nt, kt, pd>), g, b, 0, s, a); \
+        return 0; \
+    }
+    if constexpr (B == 16) { STTSM_BF16_TILES_16(STTSM_TRY) }
+    else { STTSM_BF16_TILES_8(STTSM_TRY) }
+#undef STTSM_TRY
+    return -1;
+}
+
+template <int M, int B>
+int launch_mb(int K, const StageArgs &a, int NT, int KT, int PD, const StageArgs *d_stages,
+              const GroupedTask *d_tasks, int ntasks, int *d_head, int grid, hipStream_t s)
+{
+    switch (K) {
+    case 0: return launch_one<M, B, 0>(a, NT, KT, PD, d_stages, d_tasks, ntasks, d_head, grid, s);
+    case 1: return launch_one<M, B, 1>(a, NT, KT, PD, d_stages, d_tasks, ntasks, d_head, grid, s);
+    case 2: return launch_one<M, B, 2>(a, NT, KT, PD, d_stages, d_tasks, ntasks, d_head, grid, s);
+    case 3:
+        if constexpr (M > 3) return launch_one<M, B, 3>(a, NT, KT, PD, d_stages, d_tasks, ntasks, d_head, grid, s);
+        return -1;
+    default: return -1;
+    }
+}
+
+int launch_bf16_any(int M, int B, int K, const StageArgs &a, int NT, int KT, int PD, const StageArgs *d_stages,
+                    const GroupedTask *d_tasks, int ntasks, int *d_head, int grid, hipStream_t s)
+{
+    int rc = -1;
+    if (M == 3 && B == 8) rc = launch_mb<3, 8>(K, a, NT, KT, PD, d_stages, d_tasks, ntasks, d_head, grid, s);
+    else if (M == 3 && B == 16) rc = launch_mb<3, 16>(K, a, NT, KT, PD, d_stages, d_tasks, ntasks, d_head, grid, s);
+    else if (M == 4 && B == 8) rc = launch_mb<4, 8>(K, a, NT, KT, PD, d_stages, d_tasks, ntasks, d_head, grid, s);
+    else if (M == 4 && B == 16) rc = launch_mb<4, 16>(K, a, NT, KT, PD, d_stages, d_tasks, ntasks, d_head, grid, s);
+    if (rc) return rc;
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace
+
+bool bf16_fast_supported(int m, int bA, int bC, int nbar)
+{
+    return (m == 3 || m == 4) && bA == bC && (bA == 8 || bA == 16) && nbar >= 1 && nbar <= kBf16MaxBlocks;
+}
+
+void bf16_fast_tile(int b, int *MT, int *NT, int *KT, int *PD)
+{
+    *MT = b * b;
+    if (b == 16) {
+        *NT = Bf16Default<16>::NT, *KT = Bf16Default<16>::KT, *PD = Bf16Default<16>::PD;
+    } else {
+        *NT = Bf16Default<8>::NT, *KT = Bf16Default<8>::KT, *PD = Bf16Default<8>::PD;
+    }
+}
+
+bool bf16_tile_supported(int b, int NT, int KT, int PD)
+{
+#define STTSM_HAS(nt, kt, pd) if (NT == nt && KT == kt && PD == pd) return true;
+    if (b == 16) {
+        if (NT == Bf16Default<16>::NT && KT == Bf16Default<16>::KT && PD == Bf16Default<16>::PD) return true;
+        STTSM_BF16_TILES_16(STTSM_HAS)
+    } else if (b == 8) {
+        if (NT == Bf16Default<8>::NT && KT == Bf16Default<8>::KT && PD == Bf16Default<8>::PD) return true;
+        STTSM_BF16_TILES_8(STTSM_HAS)
+    }
+#undef STTSM_HAS
+    return false;
+}
+
+int launch_stage_bf16(const StageArgs &a, int NT, int KT, int PD, hipStream_t s)
+{
+    if (a.ntasks <= 0) return 0;
+    if (!bf16_fast_supported(a.m, a.bA, a.bC, a.nbar)) return -1;
+    return launch_bf16_any(a.m, a.bA, a.k, a, NT, KT, PD, nullptr, nullptr, 0, nullptr, 0, s);
+}
+
+int launch_grouped_bf16(int m, int b, int k, const StageArgs *d_stages, const GroupedTask *d_tasks, int ntasks,
+                        int *d_head, int grid, hipStream_t s)
+{
+    if (ntasks <= 0) return 0;
+    StageArgs dummy{};
+    int MT, NT, KT, PD;
+    bf16_fast_tile(b, &MT, &NT, &KT, &PD);
+    return launch_bf16_any(m, b, k, dummy, NT, KT, PD, d_stages, d_tasks, ntasks, d_head, grid, s);
+}
+
+}  // namespace symt

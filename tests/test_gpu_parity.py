@@ -335,3 +335,64 @@ def test_block_copy_and_generic_kernels(m, n, p, bA, bC, generic, monkeypatch):
     say("  rel err", e)
     assert e <= TOL_FP32
     assert np.all(got[padding_mask(m, p, bC)] == 0.0)
+
+
+# ------------------------------------------------------------------ bf16 block-copy kernel
+# (m, n, p, b): ragged n and p, K chunks that run past nbar, m = 4 M tiles.
+BF16_FAST_SHAPES = [(3, 40, 24, 8), (3, 35, 35, 16), (3, 100, 70, 16), (3, 130, 60, 16), (4, 33, 20, 8),
+                    (4, 48, 16, 8), (4, 40, 37, 16), (4, 64, 64, 8)]
+
+
+def bf16_fast_level0_tasks(m, n, p, b):
+    """Workgroup tasks of level 0 under the bf16 block-copy tiling:
+    unique prefixes x column tiles (128 wide) x M tiles
+    (b^(m-3) of b^2 rows each)."""
+    from math import comb
+    import os
+    nbar, pbar = -(-n // b), -(-p // b)
+    nt = 128
+    override = os.environ.get("STTSM_BF16_TILE", "")   # "NTxKTxPD", a measurement override
+    if override and "," not in override:
+        o_nt = int(override.split("x")[0])
+        if (b == 16 and override in ("64x32x1", "64x32x2", "64x16x2", "64x16x3", "128x16x2", "128x32x2")) or \
+                (b == 8 and override in ("256x32x1", "128x32x2", "128x16x2", "128x16x3")):
+            nt = o_nt
+    return comb(nbar + m - 2, m - 1) * (-(-(pbar * b) // nt)) * b ** (m - 3)
+
+
+@pytest.mark.parametrize("generic", [False, True], ids=["blockcopy", "generic"])
+@pytest.mark.parametrize("m,n,p,b", BF16_FAST_SHAPES)
+def test_bf16_block_copy_and_generic_kernels(m, n, p, b, generic, monkeypatch):
+    """BF16 inputs and temporaries (the served form) through the bf16
+    block-copy kernel and through the generic kernel: both within the bf16
+    bound of the oracle run on the same bf16 values; padding exactly zero."""
+    import torch
+    if generic:
+        monkeypatch.setenv("STTSM_GENERIC_KERNELS", "1")
+    else:
+        monkeypatch.delenv("STTSM_GENERIC_KERNELS", raising=False)
+    info = st().sttsm_plan_info(m, n, p, b, b, PBF, 0, dtype=st().BF16)
+    if not generic:
+        assert info["tasks"] == bf16_fast_level0_tasks(m, n, p, b)
+    say("bf16 kernels", "generic" if generic else "block-copy", m, n, p, b, info)
+    A = synth.round_to_bf16(synth.symmetric_uniform(m, n, (m, n, p, 93)))
+    X = synth.round_to_bf16(synth.change_of_basis(p, n, (m, n, p, 94)))
+    got = run(A, X, b, b, PBF, dtype=torch.bfloat16)
+    e = err(got, ref_bcss(A.astype(np.float64), X.astype(np.float64), b), m, p, b)
+    say("  rel err", e, "bound", tol_bf16(m))
+    assert e <= tol_bf16(m)
+    assert np.all(got[padding_mask(m, p, b)] == 0.0)
+
+
+def test_bf16_block_copy_config2_full():
+    """m = 3, n = p = 256, b = 16 in bf16 through the block-copy kernel (the
+    bench workload at bf16): the whole C against the oracle chain on the same
+    bf16 values."""
+    import torch
+    m, n, p, b = 3, 256, 256, 16
+    A, X = synth.make_config_inputs("m3_n256_b16")
+    A, X = synth.round_to_bf16(A), synth.round_to_bf16(X)
+    got = run(A, X, b, b, PBF, dtype=torch.bfloat16)
+    e = err(got, ref_bcss(A.astype(np.float64), X.astype(np.float64), b), m, p, b)
+    say("config m3_n256_b16 bf16 rel err", e, "bound", tol_bf16(m))
+    assert e <= tol_bf16(m)
