@@ -106,6 +106,11 @@ def serve_bench(args):
 
     budget = int(args.serve_budget_gb * 2 ** 30)
 
+    # Requests whose C is kept for the accuracy check: small enough for the
+    # FP64 oracle chain to take well under a second each.
+    sample_ids = [r["id"] for r in shapes if r["n"] ** r["m"] * r["p"] <= 6e8][:12]
+    kept = {}
+
     def run(arrivals, window):
         """Submit in arrival order (open loop: at the arrival times; closed
         loop: keeping `window` outstanding); returns wall time and stats."""
@@ -115,13 +120,15 @@ def serve_bench(args):
 
         def drain(block):
             while pending:
-                t = pending[0]
+                t, rid = pending[0]
                 st_ = srv.wait(t, -1.0 if block else 0.0)
                 if st_ not in (st.DONE, st.FAILED):
                     return
                 if st_ == st.FAILED:
                     raise RuntimeError("served request failed")
-                srv.fetch(t)
+                C = srv.fetch(t)
+                if rid in sample_ids:
+                    kept[rid] = C.cpu()
                 pending.pop(0)
 
         for i, r in enumerate(shapes):
@@ -133,7 +140,7 @@ def serve_bench(args):
                 while len(pending) >= window:
                     drain(True)
             A, X = inputs(r)
-            pending.append(srv.submit(A, X, r["m"], r["n"], r["p"], r["b"], r["b"], st.PREC_BF16))
+            pending.append((srv.submit(A, X, r["m"], r["n"], r["p"], r["b"], r["b"], st.PREC_BF16), r["id"]))
             drain(False)
         while pending:
             drain(True)
@@ -180,6 +187,27 @@ def serve_bench(args):
         dur[i] = e0.elapsed_time(e1) * 1e-3
         del A, X, C, ws
     plain = {"req_per_s_saturated": round(N / dur.sum(), 2), "gflop_per_s": round(flops.sum() / dur.sum() / 1e9, 1)}
+    # Accuracy of served results: sampled requests against the FP64 oracle on
+    # the same bf16 inputs, and bit for bit against the plain path.
+    import oracle
+    from oracle import bcss_ref
+    errs, same = [], 0
+    for rid in sample_ids:
+        r = keep[rid]
+        m, n, p, b = r["m"], r["n"], r["p"], r["b"]
+        A64 = synth.round_to_bf16(synth.hashed_symmetric(m, n, r["seed_a"]).astype(np.float32)).astype(np.float64)
+        X64 = synth.round_to_bf16(synth.change_of_basis(p, n, r["seed_x"])).astype(np.float64)
+        nb = st.bcss_num_blocks(m, -(-p // b))
+        got = kept[rid].double().numpy().reshape(nb, b ** m)
+        ref = bcss_ref.pack(oracle.chain(A64, X64), b)
+        errs.append((bcss_ref.rel_frobenius_bcss(got, ref, m, p, b), (2 * m) ** 0.5 * 2.0 ** -8))
+        A, X = inputs(r)
+        Cp, _ = st.sttsm(A, X, m, n, p, b, b, st.PREC_BF16)
+        same += int(torch.equal(Cp.cpu(), kept[rid]))
+    accuracy = {"sampled_requests": len(sample_ids),
+                "max_rel_err_vs_fp64": float("%.3e" % max(e for e, _ in errs)),
+                "within_bf16_bound": sum(int(e <= t) for e, t in errs),
+                "bitwise_equal_to_plain": same}
     for rho in (0.5, 0.9):
         arr = out["load_%.1f" % rho].pop("_arrivals")
         t_free, lat = 0.0, np.zeros(N)
@@ -203,6 +231,7 @@ def serve_bench(args):
                    "window": args.serve_window, "total_gflop": round(flops.sum() / 1e9, 1)},
         "served": out,
         "plain_one_at_a_time": plain,
+        "accuracy": accuracy,
     }
     print(json.dumps(res), flush=True)
 

@@ -70,7 +70,8 @@ struct Bf16Cfg {
     static constexpr int RSK = KT + 8;                  // [row][kk] row stride
     static constexpr int XS = KT + 8;                   // X [nn][kk] row stride
     static constexpr int IN_ELEMS = KM ? MT * RSK : KT * RS;
-    static constexpr int WM = MT >= 128 ? 2 : 1, WN = 4 / WM;
+    // waves along M: 4 for 32-wide column tiles, else 2 (1 for 64-row tiles)
+    static constexpr int WM = NT <= 32 ? 4 : (MT >= 128 ? 2 : 1), WN = 4 / WM;
     static constexpr int WTM = MT / WM, WTN = NT / WN;
     static constexpr int TM = WTM / 32, TN = WTN / 32;
     static constexpr int G = KT / B;                    // whole blocks per K chunk
@@ -435,11 +436,11 @@ __global__ __launch_bounds__(256, 2) void grouped_fast_bf16(const StageArgs *__r
 // Default tile (NT, KT, PD) per block size; the grouped kernel always uses it.
 template <int B>
 struct Bf16Default {
-    static constexpr int NT = 128, KT = 32, PD = 1;
+    static constexpr int NT = B == 16 ? 64 : 128, KT = 32, PD = 1;
 };
 
 // Other per-level tiles (NT, KT, PD), selectable for measurement.
-#define STTSM_BF16_TILES_16(X) X(64, 32, 1) X(64, 32, 2) X(64, 16, 2) X(64, 16, 3) X(128, 16, 2) X(128, 32, 2)
+#define STTSM_BF16_TILES_16(X) X(128, 32, 1) X(64, 32, 2) X(64, 16, 2) X(128, 16, 2) X(32, 16, 1) X(32, 16, 2) X(32, 32, 1) X(32, 32, 2)
 #define STTSM_BF16_TILES_8(X) X(256, 32, 1) X(128, 32, 2) X(128, 16, 2) X(128, 16, 3)
 
 template <int M, int B, int K>

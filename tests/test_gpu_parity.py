@@ -345,16 +345,17 @@ BF16_FAST_SHAPES = [(3, 40, 24, 8), (3, 35, 35, 16), (3, 100, 70, 16), (3, 130, 
 
 def bf16_fast_level0_tasks(m, n, p, b):
     """Workgroup tasks of level 0 under the bf16 block-copy tiling:
-    unique prefixes x column tiles (128 wide) x M tiles
+    unique prefixes x column tiles (b = 16: 64 wide, b = 8: 128) x M tiles
     (b^(m-3) of b^2 rows each)."""
     from math import comb
     import os
     nbar, pbar = -(-n // b), -(-p // b)
-    nt = 128
+    nt = 64 if b == 16 else 128
     override = os.environ.get("STTSM_BF16_TILE", "")   # "NTxKTxPD", a measurement override
     if override and "," not in override:
         o_nt = int(override.split("x")[0])
-        if (b == 16 and override in ("64x32x1", "64x32x2", "64x16x2", "64x16x3", "128x16x2", "128x32x2")) or \
+        if (b == 16 and override in ("128x32x1", "64x32x2", "64x16x2", "128x16x2", "32x16x1", "32x16x2", "32x32x1",
+                                       "32x32x2")) or \
                 (b == 8 and override in ("256x32x1", "128x32x2", "128x16x2", "128x16x3")):
             nt = o_nt
     return comb(nbar + m - 2, m - 1) * (-(-(pbar * b) // nt)) * b ** (m - 3)
