@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--workload", default="m3_n256_b16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
+    ap.add_argument("--op", default="sttsm", choices=["sttsm", "all_but_one"],
+                    help="sttsm, or the product in all modes but mode 0")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum oracle time for the CPU baseline")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before timing, copy this many MiB device to device once (a plain copy kernel of known "
@@ -275,16 +277,23 @@ def main():
     X = torch.from_numpy(np.ascontiguousarray(X_np)).to(tdt).to(dev)
     A = st.bcss_pack(A_dense, m, n, bA)
     del A_dense
-    C, ws = st.sttsm(A, X, m, n, p, bA, bC, prec)
+    if args.op == "sttsm":
+        C, ws = st.sttsm(A, X, m, n, p, bA, bC, prec)
+        call = lambda: st.sttsm(A, X, m, n, p, bA, bC, prec, C=C, ws=ws)
+        nlev = m
+    else:
+        C, ws = st.sttsm_all_but_one(A, X, m, n, p, bA, bC, prec)
+        call = lambda: st.sttsm_all_but_one(A, X, m, n, p, bA, bC, prec, T=C, ws=ws)
+        nlev = m - 1
     torch.cuda.synchronize()
-    flops = st.sttsm_flops(m, n, p, bA, bC)
     levels = [st.sttsm_plan_info(m, n, p, bA, bC, prec, d, dtype=st.BF16 if args.prec == "bf16" else st.F32)
-              for d in range(m)]
+              for d in range(nlev)]
+    flops = sum(lv["flops"] for lv in levels)
     stream = torch.cuda.current_stream()
 
     log("bench: warmup", args.warmup)
     for _ in range(args.warmup):
-        st.sttsm(A, X, m, n, p, bA, bC, prec, C=C, ws=ws)
+        call()
     torch.cuda.synchronize()
 
     # Timed region 1 (the reported throughput): K steps, each one replay of
@@ -296,12 +305,12 @@ def main():
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
-            st.sttsm(A, X, m, n, p, bA, bC, prec, C=C, ws=ws)
+            call()
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
-            st.sttsm(A, X, m, n, p, bA, bC, prec, C=C, ws=ws)
+            call()
         torch.cuda.synchronize()
         for _ in range(args.warmup):
             graph.replay()
@@ -318,7 +327,7 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / args.steps, (time.perf_counter() - t) * 1e3 / args.steps
 
-    eager_step = lambda: st.sttsm(A, X, m, n, p, bA, bC, prec, C=C, ws=ws)
+    eager_step = call
     C_graph = None
     if graph is not None:
         ms_step, wall_ms = timed(graph.replay)
@@ -343,7 +352,7 @@ def main():
     # Dominant kernel: the level with the largest flop count (the first on
     # ties); its roofline is MFMA or HBM, whichever bounds it by the model
     # time = max(flops / MFMA peak, algorithmic bytes / HBM peak).
-    dom = max(range(m), key=lambda d: (levels[d]["flops"], -d))
+    dom = max(range(nlev), key=lambda d: (levels[d]["flops"], -d))
     dom_ms = prof[dom][0] / prof[dom][1]
     peak = PEAK_TFLOPS[args.prec]
     dom_bytes = level_bytes(m, n, p, bA, bC, args.prec, dom)
@@ -360,11 +369,12 @@ def main():
     roof["kernel"] = "level %d (%.3f GFLOP, %.1f MB algorithmic per launch)" % (dom, levels[dom]["flops"] / 1e9,
                                                                                  dom_bytes / 1e6)
     roof["kernel_us"] = round(dom_ms * 1e3, 3)
-    level_times = {str(d): round(prof[d][0] / prof[d][1] * 1e3, 3) for d in range(m) if d in prof}
+    level_times = {str(d): round(prof[d][0] / prof[d][1] * 1e3, 3) for d in range(nlev) if d in prof}
 
     # Accuracy of this run against the FP64 oracle (also the CPU baseline).
     out = {
-        "metric": "sttsm GFLOP/s (symmetry-aware count, Table 2 of the paper)",
+        "metric": ("sttsm" if args.op == "sttsm" else "sttsm all-modes-but-one") +
+                  " GFLOP/s (symmetry-aware count, Table 2 of the paper)",
         "value": round(gflops, 2),
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -384,6 +394,34 @@ def main():
         "roofline": roof,
     }
 
+    # Pack and unpack (HBM-bound copies through the block layout), timed
+    # apart from the step: K calls each, HIP events around the loop.
+    def timed_op(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+    esz = 2 if args.prec == "bf16" else 4
+    dense = torch.empty(n ** m, dtype=tdt, device=dev)
+    st.bcss_unpack(A, m, n, bA, out=dense)
+    A2 = torch.empty_like(A)
+    stored = st.bcss_num_elems(m, n, bA, st.BF16 if args.prec == "bf16" else st.F32)
+    ms_pack = timed_op(lambda: st.bcss_pack(dense, m, n, bA, out=A2))
+    ms_unpack = timed_op(lambda: st.bcss_unpack(A, m, n, bA, out=dense))
+    torch.cuda.synchronize()
+    if not torch.equal(A2, A):
+        raise RuntimeError("pack(unpack(A)) differs from A")
+    for name, ms, nbytes in (("pack", ms_pack, 2 * stored * esz), ("unpack", ms_unpack, (n ** m + stored) * esz)):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        out[name] = {"us": round(ms * 1e3, 2), "algorithmic_mb": round(nbytes / 1e6, 2), "achieved_gbs": round(gbs, 1),
+                     "peak_gbs": PEAK_HBM_GBS, "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    del dense, A2
+
     if not args.no_cpu_baseline:
         import oracle
         from oracle import bcss_ref
@@ -391,18 +429,35 @@ def main():
         log("bench: CPU oracle (dense chain, FP64)")
         runs, t_cpu = 0, 0.0
         Cref = None
+        ref_fn = oracle.chain if args.op == "sttsm" else oracle.all_but_one
         while t_cpu < args.cpu_seconds and runs < 20:
             t = time.perf_counter()
-            Cref = oracle.chain(A64, X64)
+            Cref = ref_fn(A64, X64)
             t_cpu += time.perf_counter() - t
             runs += 1
         cpu_gflops = flops / (t_cpu / runs) / 1e9
         out["cpu_baseline"] = {"value": round(cpu_gflops, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
                                "kind": "oracle",
                                "sample": "full workload, dense FP64 mode-product chain, %d run(s), %.1f s" % (runs, t_cpu)}
-        nb = st.bcss_num_blocks(m, -(-p // bC))
-        got = C.double().cpu().numpy().reshape(nb, bC ** m)
-        out["rel_err_vs_fp64"] = float("%.3e" % bcss_ref.rel_frobenius_bcss(got, bcss_ref.pack(Cref, bC), m, p, bC))
+        if args.op == "sttsm":
+            nb = st.bcss_num_blocks(m, -(-p // bC))
+            got = C.double().cpu().numpy().reshape(nb, bC ** m)
+            err = bcss_ref.rel_frobenius_bcss(got, bcss_ref.pack(Cref, bC), m, p, bC)
+        else:
+            # T in its [J][ibar][block] layout against the oracle's dense T
+            nbar, pbar = -(-n // bA), -(-p // bC)
+            pad = np.zeros((nbar * bA,) + (pbar * bC,) * (m - 1))
+            pad[(slice(0, n),) + tuple(slice(0, p) for _ in range(m - 1))] = Cref
+            got = C.double().cpu().numpy()
+            num = den = 0.0
+            for r, J in enumerate(bcss_ref.sorted_block_tuples(m - 1, pbar)):
+                for i in range(nbar):
+                    sl = (slice(i * bA, (i + 1) * bA),) + tuple(slice(j * bC, (j + 1) * bC) for j in J)
+                    ref = pad[sl].ravel(order="F")
+                    num += float(np.sum((got[r, i] - ref) ** 2))
+                    den += float(np.sum(ref ** 2))
+            err = (num / den) ** 0.5
+        out["rel_err_vs_fp64"] = float("%.3e" % err)
 
     print(json.dumps(out), flush=True)
 

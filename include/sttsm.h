@@ -139,6 +139,25 @@ int sttsm(const bcss_layout *A, const void *A_dev, const void *X_dev, int64_t rs
           const bcss_layout *C, void *C_dev, int32_t prec, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * "All modes but one" (the related operation §2.5 names next to sttsm): the
+ * tensor A x_1 X x_2 X ... x_{m-1} X, which multiplies every mode but mode 0
+ * and is symmetric in modes 1..m-1.  It is the temporary T^(1) of the sttsm
+ * chain (the chain stops before the last level), written to T instead of the
+ * workspace, in the layout sttsm_workspace_temp describes for k = 1:
+ * [J][s][block], J over sorted (m-1)-tuples of C-block indices (colex),
+ * s over the nbar A-block indices of mode 0, blocks of bA * bC^(m-1) entries
+ * in dimensional order (mode 0 of extent bA fastest).  Its dtype is the
+ * temporaries' dtype of `prec` (F32 for FP32 and BF16X3_FIRST_FP32, BF16
+ * otherwise).  Arguments as for sttsm; C describes the output modes (its
+ * n = p and b = bC); needs m >= 2 (EINVAL otherwise).  The workspace size is
+ * sttsm_workspace_bytes(A, C, prec).
+ */
+int sttsm_all_but_one(const bcss_layout *A, const void *A_dev, const void *X_dev, int64_t rs_x, int64_t cs_x,
+                      const bcss_layout *C, void *T_dev, int32_t prec, void *ws, size_t ws_bytes, void *stream);
+/* Entries of T for sttsm_all_but_one (padded); -1 on bad arguments or m < 2. */
+int64_t sttsm_all_but_one_elems(const bcss_layout *A, const bcss_layout *C, int32_t prec);
+
+/*
  * Where sttsm leaves temporary T^(k) (1 <= k <= m-1) inside the workspace.
  * T^(k) has extent n in modes 0..k-1 (symmetric, Theorem 1) and p in modes
  * k..m-1.  It is stored as [J][s][block]: J runs over sorted tuples

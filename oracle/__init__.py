@@ -150,3 +150,21 @@ def chain(A: np.ndarray, X: np.ndarray, keep_temps: bool = False):
     if rc:
         raise MemoryError("oracle_chain failed (%d)" % rc)
     return (C, temps) if keep_temps else C
+
+
+def all_but_one(A: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """A x_1 X x_2 X ... x_{m-1} X: the product in every mode but mode 0, the
+    related operation §2.5 names beside sttsm; dense FP64, Fortran order,
+    extent n in mode 0 and p in the others.  Computed as the same mode
+    products as chain(), in the same order, stopping before mode 0."""
+    A = _as_dense_f64(A)
+    X = np.asarray(X, dtype=np.float64)
+    _check(A, X)
+    m = A.ndim
+    if m < 2:
+        raise ValueError("needs order m >= 2")
+    T = A
+    for k in range(m - 1, 0, -1):
+        T = mode_product(T, k, X)
+    return T
+

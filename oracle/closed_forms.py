@@ -34,3 +34,16 @@ def rank_r(lams, vecs, X: np.ndarray, m: int) -> np.ndarray:
         term = lam * outer_power(X64 @ np.asarray(a, dtype=np.float64), m)
         out = term if out is None else out + term
     return np.asfortranarray(out)
+
+
+def rank_r_all_but_one(lams, vecs, X: np.ndarray, m: int) -> np.ndarray:
+    """A x_1 X ... x_{m-1} X for A = sum_i lam_i a_i^{o m}:
+    sum_i lam_i a_i o (X a_i)^{o (m-1)} (multilinearity of the mode products;
+    mode 0 keeps a_i)."""
+    X64 = np.asarray(X, dtype=np.float64)
+    out = None
+    for lam, a in zip(lams, vecs):
+        a64 = np.asarray(a, dtype=np.float64)
+        term = lam * np.multiply.outer(a64, outer_power(X64 @ a64, m - 1)) if m > 1 else lam * a64
+        out = term if out is None else out + term
+    return np.asfortranarray(out)

@@ -10,6 +10,7 @@ Names follow the C ABI in include/sttsm.h.
 from __future__ import annotations
 
 import ctypes
+import functools
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -64,6 +65,8 @@ def load():
         "bcss_fill_hashed": (ctypes.c_int, [L, ctypes.c_uint64, ctypes.c_double, ctypes.c_double, vp, vp]),
         "sttsm_workspace_bytes": (sz, [L, L, i32]),
         "sttsm": (ctypes.c_int, [L, vp, vp, i64, i64, L, vp, i32, vp, sz, vp]),
+        "sttsm_all_but_one": (ctypes.c_int, [L, vp, vp, i64, i64, L, vp, i32, vp, sz, vp]),
+        "sttsm_all_but_one_elems": (i64, [L, L, i32]),
         "sttsm_workspace_temp": (ctypes.c_int, [L, L, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(i32),
                                                 ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "sttsm_plan_info": (ctypes.c_int, [L, L, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i64),
@@ -95,7 +98,7 @@ def load():
 
 def exported_symbols():
     return ["bcss_num_blocks", "bcss_num_elems", "bcss_pack", "bcss_unpack", "bcss_fill_hashed", "sttsm_flops",
-            "sttsm_workspace_bytes", "sttsm", "sttsm_workspace_temp", "sttsm_plan_info", "sttsm_profile_enable",
+            "sttsm_workspace_bytes", "sttsm", "sttsm_all_but_one", "sttsm_all_but_one_elems", "sttsm_workspace_temp", "sttsm_plan_info", "sttsm_profile_enable",
             "sttsm_profile_read", "sttsm_profile_disable", "sttsm_request_footprint", "sttsm_server_create",
             "sttsm_submit", "sttsm_poll", "sttsm_wait", "sttsm_fetch", "sttsm_server_stats", "sttsm_server_destroy",
             "sttsm_last_error", "sttsm_version"]
@@ -153,14 +156,20 @@ def sttsm_workspace_bytes(m: int, n: int, p: int, bA: int, bC: int, prec: int = 
     return load().sttsm_workspace_bytes(ctypes.byref(layout(m, n, bA, dtype)), ctypes.byref(layout(m, p, bC)), prec)
 
 
-def sttsm_workspace_temp(m: int, n: int, p: int, bA: int, bC: int, prec: int, k: int, dtype: int = F32) -> dict:
+@functools.lru_cache(maxsize=256)
+def _workspace_temp(m, n, p, bA, bC, prec, k, dtype):
     off, dt = ctypes.c_size_t(), ctypes.c_int32()
     nj, npf, blk = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     _check(load().sttsm_workspace_temp(ctypes.byref(layout(m, n, bA, dtype)), ctypes.byref(layout(m, p, bC)), prec,
                                        k, ctypes.byref(off), ctypes.byref(dt), ctypes.byref(nj),
                                        ctypes.byref(npf), ctypes.byref(blk)))
-    return dict(byte_offset=off.value, dtype=dt.value, num_jtuples=nj.value, num_prefixes=npf.value,
-                block_elems=blk.value)
+    return (off.value, dt.value, nj.value, npf.value, blk.value)
+
+
+def sttsm_workspace_temp(m: int, n: int, p: int, bA: int, bC: int, prec: int, k: int, dtype: int = F32) -> dict:
+    """Where T^(k) sits in sttsm's workspace (cached per shape)."""
+    off, dt, nj, npf, blk = _workspace_temp(int(m), int(n), int(p), int(bA), int(bC), int(prec), int(k), int(dtype))
+    return dict(byte_offset=off, dtype=dt, num_jtuples=nj, num_prefixes=npf, block_elems=blk)
 
 
 def sttsm_plan_info(m: int, n: int, p: int, bA: int, bC: int, prec: int, level: int, dtype: int = F32) -> dict:
@@ -239,6 +248,37 @@ def sttsm(A_bcss, X, m: int, n: int, p: int, bA: int, bC: int, prec: int = PREC_
     _check(load().sttsm(ctypes.byref(LA), _ptr(A_bcss), X.data_ptr(), X.stride(0), X.stride(1),
                         ctypes.byref(LC), _ptr(C), prec, _ptr(ws), ws.numel(), _stream(stream)))
     return C, ws
+
+
+def sttsm_all_but_one(A_bcss, X, m: int, n: int, p: int, bA: int, bC: int, prec: int = PREC_FP32, T=None,
+                      ws=None, stream=None):
+    """T := A x_1 X ... x_{m-1} X (every mode but mode 0), laid out as the
+    temporary T^(1): a tensor (num_jtuples, nbar, bA * bC^(m-1)) of the
+    temporaries' dtype.  Returns (T, ws)."""
+    import torch
+    dt = _torch_dtype_code(A_bcss)
+    if X.dtype != A_bcss.dtype or X.dim() != 2 or tuple(X.shape) != (p, n):
+        raise ValueError("X must be a (p, n) tensor of A's dtype")
+    LA, LC = layout(m, n, bA, dt), layout(m, p, bC, F32)
+    if A_bcss.numel() < bcss_num_elems(m, n, bA, dt):
+        raise ValueError("A too small for its layout")
+    info = sttsm_workspace_temp(m, n, p, bA, bC, prec, 1, dt)
+    ne = load().sttsm_all_but_one_elems(ctypes.byref(LA), ctypes.byref(LC), prec)
+    if ne < 0:
+        raise SttsmError(-1, load().sttsm_last_error().decode())
+    tdt = _torch_dtype(info["dtype"])
+    if T is None:
+        T = torch.empty(ne, dtype=tdt, device=A_bcss.device)
+    elif T.numel() < ne or T.dtype != tdt:
+        raise ValueError("T too small or of the wrong dtype")
+    wsb = load().sttsm_workspace_bytes(ctypes.byref(LA), ctypes.byref(LC), prec)
+    if wsb == 0:
+        raise SttsmError(-1, load().sttsm_last_error().decode())
+    if ws is None or ws.numel() < wsb:
+        ws = torch.empty(wsb, dtype=torch.uint8, device=A_bcss.device)
+    _check(load().sttsm_all_but_one(ctypes.byref(LA), _ptr(A_bcss), X.data_ptr(), X.stride(0), X.stride(1),
+                                    ctypes.byref(LC), _ptr(T), prec, _ptr(ws), ws.numel(), _stream(stream)))
+    return T[:ne].view(info["num_jtuples"], info["num_prefixes"], info["block_elems"]), ws
 
 
 def temporary(ws, m: int, n: int, p: int, bA: int, bC: int, prec: int, k: int, dtype: int = F32):

@@ -249,18 +249,27 @@ int sttsm_plan_info(const bcss_layout *A, const bcss_layout *C, int32_t prec, in
     return STTSM_OK;
 }
 
-int sttsm(const bcss_layout *A, const void *A_dev, const void *X_dev, int64_t rs_x, int64_t cs_x,
-          const bcss_layout *C, void *C_dev, int32_t prec, void *ws, size_t ws_bytes, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Levels 0..last of the plan for (A, C, prec); level `last` writes to `out`
+// (C when last = m-1, the caller's T^(1) when last = m-2).
+int run_levels(const bcss_layout *A, const void *A_dev, const void *X_dev, int64_t rs_x, int64_t cs_x,
+               const bcss_layout *C, int32_t prec, int last_from_end, void *out, void *ws, size_t ws_bytes,
+               void *stream)
 {
     PlanKey key;
     int rc = make_key(A, C, prec, &key);
     if (rc != STTSM_OK) return rc;
-    if (!A_dev || !X_dev || !C_dev) return fail(STTSM_EINVAL, "null buffer");
+    if (!A_dev || !X_dev || !out) return fail(STTSM_EINVAL, "null buffer");
     if (((uintptr_t)ws & 255) != 0) return fail(STTSM_EINVAL, "workspace must be 256-byte aligned");
     std::string why;
     const Plan *P = plan_get(key, &why);
     if (!P) return fail(STTSM_ENOMEM, why);
     if (ws_bytes < P->ws_bytes || (!ws && P->ws_bytes)) return fail(STTSM_EINVAL, "workspace too small");
+    const int last = (int)P->stages.size() - 1 - last_from_end;
+    if (last < 0) return fail(STTSM_EINVAL, "order too small for this operation");
     hipStream_t s = as_stream(stream);
     char *w = (char *)ws;
     float *x32 = P->xp_off[0] >= 0 ? (float *)(w + P->xp_off[0]) : nullptr;
@@ -273,10 +282,11 @@ int sttsm(const bcss_layout *A, const void *A_dev, const void *X_dev, int64_t rs
     if (xt && launch_prep_xt(dtype_size(A->dtype), X_dev, rs_x, cs_x, P->p, P->n, P->Kt, P->Pt, xt, s))
         return fail(STTSM_EHIP, std::string("X panel launch failed: ") + hipGetErrorString(hipGetLastError()));
     const void *slot_ptr[4] = {x32, xhi, xlo, xt};
-    for (const StagePlan &S : P->stages) {
+    for (int d = 0; d <= last; ++d) {
+        const StagePlan &S = P->stages[d];
         StageArgs a = S.args;
         a.in = S.in_ws < 0 ? A_dev : (const void *)(w + S.in_ws);
-        a.out = S.out_ws < 0 ? C_dev : (void *)(w + S.out_ws);
+        a.out = d == last ? out : (void *)(w + S.out_ws);
         a.xp = slot_ptr[S.xp_slot];
         a.xp_lo = S.xp_lo_slot >= 0 ? slot_ptr[S.xp_lo_slot] : nullptr;
         const long slot = prof_slot(S.d);
@@ -289,6 +299,40 @@ int sttsm(const bcss_layout *A, const void *A_dev, const void *X_dev, int64_t rs
         if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot + 1], s);
     }
     return STTSM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sttsm(const bcss_layout *A, const void *A_dev, const void *X_dev, int64_t rs_x, int64_t cs_x,
+          const bcss_layout *C, void *C_dev, int32_t prec, void *ws, size_t ws_bytes, void *stream)
+{
+    return run_levels(A, A_dev, X_dev, rs_x, cs_x, C, prec, 0, C_dev, ws, ws_bytes, stream);
+}
+
+int64_t sttsm_all_but_one_elems(const bcss_layout *A, const bcss_layout *C, int32_t prec)
+{
+    PlanKey key;
+    if (make_key(A, C, prec, &key) != STTSM_OK) return -1;
+    if (A->m < 2) {
+        fail(STTSM_EINVAL, "all modes but one needs m >= 2");
+        return -1;
+    }
+    Plan P;
+    std::string why;
+    if (!plan_build_host(key, &P, &why)) {
+        fail(STTSM_EINVAL, why);
+        return -1;
+    }
+    return P.temp_jtuples[1] * P.temp_prefixes[1] * P.temp_block[1];
+}
+
+int sttsm_all_but_one(const bcss_layout *A, const void *A_dev, const void *X_dev, int64_t rs_x, int64_t cs_x,
+                      const bcss_layout *C, void *T_dev, int32_t prec, void *ws, size_t ws_bytes, void *stream)
+{
+    if (A && A->m < 2) return fail(STTSM_EINVAL, "all modes but one needs m >= 2");
+    return run_levels(A, A_dev, X_dev, rs_x, cs_x, C, prec, 1, T_dev, ws, ws_bytes, stream);
 }
 
 int sttsm_profile_enable(int32_t max_launches)

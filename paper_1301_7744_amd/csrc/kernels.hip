@@ -25,75 +25,115 @@ __device__ __forceinline__ u16 f2bf(float f)
 __device__ __forceinline__ float bf2f(u16 h) { return __uint_as_float(((uint32_t)h) << 16); }
 
 // ------------------------------------------------------------------ pack/unpack
-// One thread per BCSS entry: block r (colex), local offset l (dimensional
-// order).  Reads the dense entry, or writes zero beyond n.
+// Both kernels give one workgroup a whole block (grid-stride over blocks), so
+// the block's index tuple, its meta-data and its base offsets are uniform,
+// and let each thread move a run of 4 consecutive entries along mode 0, the
+// fastest mode of both layouts: a wave reads and writes contiguous 4-entry
+// runs, and only the digits of the run's row (modes 1..m-1) are divided out.
+
+// Stored block r (colex) of BCSS <- its sorted block of the dense tensor;
+// entries beyond n are written as zero.
 template <class E>
-__global__ void bcss_pack_kernel(const E *__restrict__ dense, E *__restrict__ bcss, int m, int64_t n,
-                                 int b, int64_t bm, int64_t total, const int32_t *__restrict__ tuples)
+__global__ void bcss_pack_kernel(const E *__restrict__ dense, E *__restrict__ bcss, int m, int64_t n, int b,
+                                 int64_t bm, int64_t nblocks, const int32_t *__restrict__ tuples, int rows,
+                                 int runs)
 {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = e / bm;
-        int64_t l = e - r * bm;
-        int64_t off = 0, npow = 1;
-        bool ok = true;
+    for (int64_t r = blockIdx.x; r < nblocks; r += gridDim.x) {
+        int64_t base = 0, npow = 1;
+        int64_t s0b = 0;
+        int32_t sb[kMaxOrder];
         for (int j = 0; j < m; ++j) {
-            const int64_t lj = l % b;
-            l /= b;
-            const int64_t ij = (int64_t)tuples[r * m + j] * b + lj;
-            ok = ok && ij < n;
-            off += ij * npow;
+            sb[j] = tuples[r * m + j] * b;
+            base += (int64_t)sb[j] * npow;
             npow *= n;
         }
-        bcss[e] = ok ? dense[off] : E(0);
-    }
-}
-
-// One thread per dense entry: its block t and local index l; the meta-data
-// tensor gives the stored block sort(t) and the permuted strides.
-template <class E>
-__global__ void bcss_unpack_kernel(const E *__restrict__ bcss, E *__restrict__ dense, int m, int64_t n,
-                                   int b, int nbar, int64_t bm, int64_t total, const int64_t *__restrict__ rank,
-                                   const int32_t *__restrict__ perm, const int32_t *__restrict__ pstr)
-{
-    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < total;
-         f += (int64_t)gridDim.x * blockDim.x) {
-        int64_t r = f;
-        int64_t meta = 0, mpow = 1;
-        int32_t loc[kMaxOrder];
-        for (int j = 0; j < m; ++j) {
-            const int64_t ij = r % n;
-            r /= n;
-            const int64_t tj = ij / b;
-            loc[j] = (int32_t)(ij - tj * b);
-            meta += tj * mpow;
-            mpow *= nbar;
+        s0b = sb[0];
+        const int64_t lim0 = n - s0b;   // valid entries along mode 0
+        E *out = bcss + r * bm;
+        for (int t = threadIdx.x; t < rows * runs; t += blockDim.x) {
+            const int row = t / runs, e0 = (t - row * runs) * 4;
+            int rr = row;
+            int64_t off = base, np = n;
+            bool ok = true;
+            for (int j = 1; j < m; ++j) {
+                const int lj = rr % b;
+                rr /= b;
+                ok = ok && (int64_t)sb[j] + lj < n;
+                off += (int64_t)lj * np;
+                np *= n;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int le = e0 + e;
+                if (le < b) out[(int64_t)row * b + le] = (ok && le < lim0) ? dense[off + le] : E(0);
+            }
         }
-        const int32_t *ps = pstr + (int64_t)perm[meta] * m;
-        int64_t off = rank[meta] * bm;
-        for (int j = 0; j < m; ++j) off += (int64_t)loc[j] * ps[j];
-        dense[f] = bcss[off];
+    }
+}
+
+// Dense block t (dimensional order over nbar^m) <- stored block sort(t), read
+// through the permuted strides of the meta-data tensor (App. B).
+template <class E>
+__global__ void bcss_unpack_kernel(const E *__restrict__ bcss, E *__restrict__ dense, int m, int64_t n, int b,
+                                   int nbar, int64_t bm, int64_t nbm, const int64_t *__restrict__ rank,
+                                   const int32_t *__restrict__ perm, const int32_t *__restrict__ pstr, int rows,
+                                   int runs)
+{
+    for (int64_t tb = blockIdx.x; tb < nbm; tb += gridDim.x) {
+        int32_t tbj[kMaxOrder], ps[kMaxOrder];
+        int64_t base = 0, npow = 1, q = tb;
+        const int32_t *pp = pstr + (int64_t)perm[tb] * m;
+        for (int j = 0; j < m; ++j) {
+            tbj[j] = (int32_t)(q % nbar) * b;
+            q /= nbar;
+            base += (int64_t)tbj[j] * npow;
+            npow *= n;
+            ps[j] = pp[j];
+        }
+        const E *src = bcss + rank[tb] * bm;
+        const int64_t lim0 = n - tbj[0];
+        for (int t = threadIdx.x; t < rows * runs; t += blockDim.x) {
+            const int row = t / runs, e0 = (t - row * runs) * 4;
+            int rr = row;
+            int64_t off = base, np = n, so = 0;
+            bool ok = true;
+            for (int j = 1; j < m; ++j) {
+                const int lj = rr % b;
+                rr /= b;
+                ok = ok && (int64_t)tbj[j] + lj < n;
+                off += (int64_t)lj * np;
+                so += (int64_t)lj * ps[j];
+                np *= n;
+            }
+            if (!ok) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int le = e0 + e;
+                if (le < b && le < lim0) dense[off + le] = src[so + (int64_t)le * ps[0]];
+            }
+        }
     }
 }
 
 template <class E>
-static int launch_pack_t(const void *dense, void *bcss, int m, int64_t n, int b, int64_t bm, int64_t total,
+static int launch_pack_t(const void *dense, void *bcss, int m, int64_t n, int b, int64_t bm, int64_t nblocks,
                          const int32_t *tuples, hipStream_t s)
 {
-    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 1 << 20);
-    hipLaunchKernelGGL(bcss_pack_kernel<E>, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, s,
-                       (const E *)dense, (E *)bcss, m, n, b, bm, total, tuples);
+    const int rows = (int)(bm / b), runs = (b + 3) / 4;
+    const int64_t grid = std::min<int64_t>(std::max<int64_t>(nblocks, 1), 1 << 16);
+    hipLaunchKernelGGL(bcss_pack_kernel<E>, dim3((unsigned)grid), dim3(256), 0, s, (const E *)dense, (E *)bcss, m,
+                       n, b, bm, nblocks, tuples, rows, runs);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <class E>
 static int launch_unpack_t(const void *bcss, void *dense, int m, int64_t n, int b, int nbar, int64_t bm,
-                           int64_t total, const int64_t *rank, const int32_t *perm, const int32_t *pstr,
-                           hipStream_t s)
+                           int64_t nbm, const int64_t *rank, const int32_t *perm, const int32_t *pstr, hipStream_t s)
 {
-    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 1 << 20);
-    hipLaunchKernelGGL(bcss_unpack_kernel<E>, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, s,
-                       (const E *)bcss, (E *)dense, m, n, b, nbar, bm, total, rank, perm, pstr);
+    const int rows = (int)(bm / b), runs = (b + 3) / 4;
+    const int64_t grid = std::min<int64_t>(std::max<int64_t>(nbm, 1), 1 << 16);
+    hipLaunchKernelGGL(bcss_unpack_kernel<E>, dim3((unsigned)grid), dim3(256), 0, s, (const E *)bcss, (E *)dense,
+                       m, n, b, nbar, bm, nbm, rank, perm, pstr, rows, runs);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -102,21 +142,22 @@ int launch_pack(int esize, const void *dense, void *bcss, int m, int64_t n, int 
 {
     int64_t bm = 1;
     for (int j = 0; j < m; ++j) bm *= b;
-    const int64_t total = bm * nblocks;
-    if (esize == 2) return launch_pack_t<uint16_t>(dense, bcss, m, n, b, bm, total, d_tuples, s);
-    if (esize == 4) return launch_pack_t<uint32_t>(dense, bcss, m, n, b, bm, total, d_tuples, s);
-    if (esize == 8) return launch_pack_t<uint64_t>(dense, bcss, m, n, b, bm, total, d_tuples, s);
+    if (bm / b * ((b + 3) / 4) > INT32_MAX / 2) return -1;
+    if (esize == 2) return launch_pack_t<uint16_t>(dense, bcss, m, n, b, bm, nblocks, d_tuples, s);
+    if (esize == 4) return launch_pack_t<uint32_t>(dense, bcss, m, n, b, bm, nblocks, d_tuples, s);
+    if (esize == 8) return launch_pack_t<uint64_t>(dense, bcss, m, n, b, bm, nblocks, d_tuples, s);
     return -1;
 }
 
 int launch_unpack(int esize, const void *bcss, void *dense, int m, int64_t n, int b, int nbar,
                   const int64_t *d_rank, const int32_t *d_perm, const int32_t *d_pstr, hipStream_t s)
 {
-    int64_t bm = 1, total = 1;
-    for (int j = 0; j < m; ++j) { bm *= b; total *= n; }
-    if (esize == 2) return launch_unpack_t<uint16_t>(bcss, dense, m, n, b, nbar, bm, total, d_rank, d_perm, d_pstr, s);
-    if (esize == 4) return launch_unpack_t<uint32_t>(bcss, dense, m, n, b, nbar, bm, total, d_rank, d_perm, d_pstr, s);
-    if (esize == 8) return launch_unpack_t<uint64_t>(bcss, dense, m, n, b, nbar, bm, total, d_rank, d_perm, d_pstr, s);
+    int64_t bm = 1, nbm = 1;
+    for (int j = 0; j < m; ++j) { bm *= b; nbm *= nbar; }
+    if (bm / b * ((b + 3) / 4) > INT32_MAX / 2) return -1;
+    if (esize == 2) return launch_unpack_t<uint16_t>(bcss, dense, m, n, b, nbar, bm, nbm, d_rank, d_perm, d_pstr, s);
+    if (esize == 4) return launch_unpack_t<uint32_t>(bcss, dense, m, n, b, nbar, bm, nbm, d_rank, d_perm, d_pstr, s);
+    if (esize == 8) return launch_unpack_t<uint64_t>(bcss, dense, m, n, b, nbar, bm, nbm, d_rank, d_perm, d_pstr, s);
     return -1;
 }
 

@@ -133,3 +133,18 @@ def test_request_footprint():
     ws = st.sttsm_workspace_bytes(3, 64, 32, 8, 8, st.PREC_BF16, st.BF16)
     assert f2 > ws + st.bcss_num_elems(3, 32, 8) * 4
     assert st.request_footprint(0, 64, 32, 8, 8, st.PREC_BF16, st.BF16) == 0
+
+
+def test_all_but_one_host_checks():
+    """All modes but one: element count is T^(1)'s, m = 1 is rejected before
+    any launch."""
+    lib = st.load()
+    LA, LC = st.layout(3, 35, 16), st.layout(3, 20, 8)
+    info = st.sttsm_workspace_temp(3, 35, 20, 16, 8, st.PREC_FP32, 1)
+    ne = lib.sttsm_all_but_one_elems(ctypes.byref(LA), ctypes.byref(LC), st.PREC_FP32)
+    assert ne == info["num_jtuples"] * info["num_prefixes"] * info["block_elems"]
+    assert info["num_jtuples"] == comb(3 + 2 - 1, 2) and info["num_prefixes"] == 3
+    L1A, L1C = st.layout(1, 10, 4), st.layout(1, 6, 4)
+    assert lib.sttsm_all_but_one_elems(ctypes.byref(L1A), ctypes.byref(L1C), st.PREC_FP32) == -1
+    rc = lib.sttsm_all_but_one(ctypes.byref(L1A), 1, 1, 10, 1, ctypes.byref(L1C), 1, st.PREC_FP32, None, 0, None)
+    assert rc == -1

@@ -397,3 +397,45 @@ def test_bf16_block_copy_config2_full():
     e = err(got, ref_bcss(A.astype(np.float64), X.astype(np.float64), b), m, p, b)
     say("config m3_n256_b16 bf16 rel err", e, "bound", tol_bf16(m))
     assert e <= tol_bf16(m)
+
+
+# ------------------------------------------------------------------ all modes but one
+def _blocks_of_T1(dense, m, n, p, bA, bC):
+    """Oracle's dense A x_1 X ... x_{m-1} X cut into the [J][ibar][block] layout."""
+    nbar, pbar = -(-n // bA), -(-p // bC)
+    pad = np.zeros((nbar * bA,) + (pbar * bC,) * (m - 1))
+    pad[(slice(0, n),) + tuple(slice(0, p) for _ in range(m - 1))] = dense
+    out = []
+    for J in bcss_ref.sorted_block_tuples(m - 1, pbar):
+        row = []
+        for i in range(nbar):
+            sl = (slice(i * bA, (i + 1) * bA),) + tuple(slice(j * bC, (j + 1) * bC) for j in J)
+            row.append(pad[sl].ravel(order="F"))
+        out.append(row)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("case", [(3, 16, 16, 4, 4, P32), (4, 9, 7, 4, 3, P32), (3, 35, 20, 16, 8, P32),
+                                  (2, 70, 33, 16, 8, P32), (3, 70, 40, 16, 16, PBF), (4, 33, 20, 8, 8, PBF)])
+def test_all_but_one_vs_oracle(case):
+    """sttsm_all_but_one (the chain stopped before mode 0) against the
+    oracle's mode products in modes m-1..1, block by block."""
+    import torch
+    m, n, p, bA, bC, prec = case
+    say("all-but-one", case)
+    A = synth.symmetric_uniform(m, n, (m, n, 71))
+    X = synth.change_of_basis(p, n, (m, n, 72))
+    tdt = torch.float32
+    if prec == PBF:
+        A, X, tdt = synth.round_to_bf16(A), synth.round_to_bf16(X), torch.bfloat16
+    Ab = st().bcss_pack(dev_dense(np.asarray(A, np.float32), tdt), m, n, bA)
+    Xd = torch.from_numpy(np.ascontiguousarray(X, np.float32)).to(tdt).cuda()
+    T, _ = st().sttsm_all_but_one(Ab, Xd, m, n, p, bA, bC, prec)
+    torch.cuda.synchronize()
+    got = T.double().cpu().numpy()
+    ref = _blocks_of_T1(oracle.all_but_one(A.astype(np.float64), X.astype(np.float64)), m, n, p, bA, bC)
+    e = float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel()))
+    bound = TOL_FP32 if prec == P32 else tol_bf16(m)
+    say("  rel err", e, "bound", bound)
+    assert got.shape == ref.shape
+    assert e <= bound

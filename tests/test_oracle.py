@@ -184,3 +184,32 @@ def test_pins_catch_a_dropped_term():
     Xbad = X.copy()
     Xbad[:, -1] = 0.0
     assert rel(oracle.chain(A, Xbad), closed_forms.rank_r(lams, vecs, X, m)) > 1e-3
+
+
+# ---------------------------------------------------------------- all modes but one
+@pytest.mark.parametrize("n,p", [(5, 3), (7, 7), (4, 6)])
+def test_all_but_one_matrix_case(n, p):
+    """m = 2: A x_1 X is A X^T (library matrix product)."""
+    A = sym(2, n, 61)
+    X = synth.change_of_basis(p, n, 62).astype(np.float64)
+    assert rel(oracle.all_but_one(A, X), A @ X.T) <= TOL
+
+
+@pytest.mark.parametrize("m,n,p,r", [(3, 6, 4, 2), (4, 5, 3, 3), (5, 4, 4, 1)])
+def test_all_but_one_rank_r(m, n, p, r):
+    """Rank-r A: sum_i lam_i a_i o (X a_i)^{o (m-1)}."""
+    lams, vecs = synth.rank_r_factors(n, r, (m, n, 63))
+    A = synth.rank_r_symmetric(m, lams, vecs)
+    X = synth.change_of_basis(p, n, (m, 64)).astype(np.float64)
+    assert rel(oracle.all_but_one(A, X), closed_forms.rank_r_all_but_one(lams, vecs, X, m)) <= 1e-12
+
+
+@pytest.mark.parametrize("m,n,p", [(3, 5, 4), (4, 4, 3)])
+def test_all_but_one_symmetry_and_last_mode(m, n, p):
+    """Symmetric in modes 1..m-1; multiplying its mode 0 by X gives sttsm's C."""
+    A = sym(m, n, (m, 65))
+    X = synth.change_of_basis(p, n, (m, 66)).astype(np.float64)
+    T = oracle.all_but_one(A, X)
+    for perm in itertools.permutations(range(1, m)):
+        assert rel(np.transpose(T, (0,) + perm), T) <= TOL
+    assert rel(oracle.mode_product(T, 0, X), oracle.direct_sum(A, X)) <= 1e-12
