@@ -421,6 +421,18 @@ def main():
         out[name] = {"us": round(ms * 1e3, 2), "algorithmic_mb": round(nbytes / 1e6, 2), "achieved_gbs": round(gbs, 1),
                      "peak_gbs": PEAK_HBM_GBS, "frac": round(gbs / PEAK_HBM_GBS, 4)}
     del dense, A2
+    if args.op == "sttsm":
+        from math import comb
+        C2 = C.clone()
+        ms_sym = timed_op(lambda: st.bcss_symmetrize(C2, m, p, bC))
+        pbar = -(-p // bC)
+        rep_blocks = comb(pbar + m - 1, m) - comb(pbar, m)       # blocks with a repeated index
+        nbytes = 2 * rep_blocks * bC ** m * 4
+        gbs = nbytes / (ms_sym * 1e-3) / 1e9
+        out["symmetrize"] = {"us": round(ms_sym * 1e3, 2), "algorithmic_mb": round(nbytes / 1e6, 2),
+                             "achieved_gbs": round(gbs, 1), "peak_gbs": PEAK_HBM_GBS,
+                             "frac": round(gbs / PEAK_HBM_GBS, 4)}
+        del C2
 
     if not args.no_cpu_baseline:
         import oracle

@@ -101,6 +101,20 @@ int bcss_pack(const bcss_layout *L, const void *dense, void *bcss, void *stream)
  * padding is dropped.  Same buffer sizes as bcss_pack. */
 int bcss_unpack(const bcss_layout *L, const void *bcss, void *dense, void *stream);
 
+/*
+ * In-place symmetrisation of a BCSS tensor, the post-processing step the end
+ * of §5.4 suggests for the rounding-level asymmetry inside blocks whose
+ * block indices repeat (sttsm computes each entry of such a block on its
+ * own).  Every entry of such a block becomes the average of its orbit under
+ * the block's stabiliser, the permutations of modes that carry equal block
+ * indices; afterwards mirrored entries are bitwise equal.  Blocks with
+ * distinct block indices are not touched.  The result equals packing the
+ * average of the dense tensor over all m! mode permutations.  Averages are
+ * summed in fp32 (f64 for F64 tensors) in a fixed order; bf16 results are
+ * rounded to nearest even.  Needs ceil(n/b)^m <= 2^24 (else ENOMEM).
+ */
+int bcss_symmetrize(const bcss_layout *L, void *bcss, void *stream);
+
 /* Fills a BCSS tensor with a symmetric pseudo-random tensor, for tests and
  * benchmarks that cannot afford a dense original: the entry with sorted
  * index s_0 <= ... <= s_{m-1} is lo + (hi - lo) u, u = (h >> 40) 2^-24,

@@ -108,3 +108,15 @@ def rel_frobenius_bcss(got: np.ndarray, ref: np.ndarray, m: int, p: int, b: int)
     num = float(np.sum(w * np.sum(d * d, axis=1)))
     den = float(np.sum(w * np.sum(np.asarray(ref, np.float64) ** 2, axis=1)))
     return (num / den) ** 0.5 if den > 0 else num ** 0.5
+
+
+def symmetrize(bcss: np.ndarray, m: int, n: int, b: int) -> np.ndarray:
+    """The post-processing of §5.4 that removes the asymmetry inside blocks:
+    the dense tensor BCSS represents (unpack), averaged over all m! mode
+    permutations, packed again.  FP64; returns (num_blocks, b^m)."""
+    D = unpack(np.asarray(bcss, dtype=np.float64), m, n, b)
+    acc = np.zeros_like(D)
+    perms = list(itertools.permutations(range(m)))
+    for p in perms:
+        acc += np.transpose(D, p)
+    return pack(acc / len(perms), b)

@@ -63,6 +63,7 @@ def load():
         "bcss_unpack": (ctypes.c_int, [L, vp, vp, vp]),
         "sttsm_flops": (i64, [L, L]),
         "bcss_fill_hashed": (ctypes.c_int, [L, ctypes.c_uint64, ctypes.c_double, ctypes.c_double, vp, vp]),
+        "bcss_symmetrize": (ctypes.c_int, [L, vp, vp]),
         "sttsm_workspace_bytes": (sz, [L, L, i32]),
         "sttsm": (ctypes.c_int, [L, vp, vp, i64, i64, L, vp, i32, vp, sz, vp]),
         "sttsm_all_but_one": (ctypes.c_int, [L, vp, vp, i64, i64, L, vp, i32, vp, sz, vp]),
@@ -97,7 +98,8 @@ def load():
 
 
 def exported_symbols():
-    return ["bcss_num_blocks", "bcss_num_elems", "bcss_pack", "bcss_unpack", "bcss_fill_hashed", "sttsm_flops",
+    return ["bcss_num_blocks", "bcss_num_elems", "bcss_pack", "bcss_unpack", "bcss_fill_hashed", "bcss_symmetrize",
+            "sttsm_flops",
             "sttsm_workspace_bytes", "sttsm", "sttsm_all_but_one", "sttsm_all_but_one_elems", "sttsm_workspace_temp", "sttsm_plan_info", "sttsm_profile_enable",
             "sttsm_profile_read", "sttsm_profile_disable", "sttsm_request_footprint", "sttsm_server_create",
             "sttsm_submit", "sttsm_poll", "sttsm_wait", "sttsm_fetch", "sttsm_server_stats", "sttsm_server_destroy",
@@ -221,6 +223,16 @@ def bcss_unpack(bcss, m: int, n: int, b: int, out=None, stream=None):
         raise ValueError("output too small or of the wrong dtype")
     _check(load().bcss_unpack(ctypes.byref(layout(m, n, b, dt)), _ptr(bcss), _ptr(out), _stream(stream)))
     return out
+
+
+def bcss_symmetrize(bcss, m: int, n: int, b: int, stream=None):
+    """Average every entry of each block with repeated block indices over
+    the block's stabiliser, in place; returns the tensor."""
+    dt = _torch_dtype_code(bcss)
+    if bcss.numel() < bcss_num_elems(m, n, b, dt):
+        raise ValueError("BCSS tensor too small")
+    _check(load().bcss_symmetrize(ctypes.byref(layout(m, n, b, dt)), _ptr(bcss), _stream(stream)))
+    return bcss
 
 
 def sttsm(A_bcss, X, m: int, n: int, p: int, bA: int, bC: int, prec: int = PREC_FP32, C=None, ws=None,

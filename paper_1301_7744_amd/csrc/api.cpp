@@ -166,6 +166,24 @@ int bcss_unpack(const bcss_layout *L, const void *bcss, void *dense, void *strea
     return STTSM_OK;
 }
 
+int bcss_symmetrize(const bcss_layout *L, void *bcss, void *stream)
+{
+    std::string why;
+    if (!layout_ok(L, &why)) return fail(STTSM_EINVAL, why);
+    if (!bcss) return fail(STTSM_EINVAL, "null buffer");
+    const int64_t ne = bcss_num_elems(L);
+    if (ne < 0) return fail(STTSM_EINVAL, "BCSS size overflows");
+    const int nbar = (int)((L->n + L->b - 1) / L->b);
+    const MetaTable *T = meta_get(L->m, nbar, L->b, &why);
+    if (!T) return fail(STTSM_ENOMEM, why);
+    const StabTable *S = stab_get(L->m, &why);
+    if (!S) return fail(STTSM_ENOMEM, why);
+    if (launch_symmetrize(L->dtype, bcss, L->m, L->b, bcss_num_blocks(L->m, nbar), T->d_tuples, S->d_start, S->d_perm,
+                          as_stream(stream)))
+        return fail(STTSM_EHIP, std::string("symmetrize launch failed: ") + hipGetErrorString(hipGetLastError()));
+    return STTSM_OK;
+}
+
 int bcss_fill_hashed(const bcss_layout *L, uint64_t seed, double lo, double hi, void *bcss, void *stream)
 {
     std::string why;

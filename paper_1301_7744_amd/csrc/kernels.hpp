@@ -1,4 +1,4 @@
-// Launchers of the gfx950 kernels (defined in kernels.hip and stage_bf16.hip).  Each returns 0,
+// Launchers of the gfx950 kernels (defined in kernels.hip, stage_bf16.hip and symmetrize.hip).  Each returns 0,
 // or -1 when the launch could not be made.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -33,6 +33,9 @@ bool bf16_tile_supported(int b, int NT, int KT, int PD);
 int launch_stage_bf16(const StageArgs &a, int NT, int KT, int PD, hipStream_t s);
 int launch_grouped_bf16(int m, int b, int k, const StageArgs *d_stages, const GroupedTask *d_tasks, int ntasks,
                         int *d_head, int grid, hipStream_t s);
+// In-place symmetrisation of the blocks with repeated indices (symmetrize.hip).
+int launch_symmetrize(int dtype, void *bcss, int m, int b, int64_t nblocks, const int32_t *d_tuples,
+                      const int32_t *d_stab_start, const uint8_t *d_stab_perm, hipStream_t s);
 int launch_prep_xt(int esize, const void *X, int64_t rs, int64_t cs, int64_t p, int64_t n, int64_t Kt, int64_t Pt,
                    float *xt, hipStream_t s);
 

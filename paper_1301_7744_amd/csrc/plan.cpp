@@ -614,4 +614,47 @@ const MetaTable *meta_get(int m, int nbar, int b, std::string *err)
     return out;
 }
 
+namespace {
+std::map<std::pair<int, int>, std::unique_ptr<StabTable>> g_stab;   // (device, m)
+}
+
+const StabTable *stab_get(int m, std::string *err)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        *err = "hipGetDevice failed";
+        return nullptr;
+    }
+    if (m < 1 || m > kMaxOrder) {
+        *err = "bad order";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    auto it = g_stab.find({dev, m});
+    if (it != g_stab.end()) return it->second.get();
+    std::unique_ptr<StabTable> T(new StabTable);
+    T->m = m;
+    const int nmask = 1 << (m - 1);
+    for (int mask = 0; mask < nmask; ++mask) {
+        // run id of every position
+        int run[kMaxOrder];
+        run[0] = 0;
+        for (int j = 1; j < m; ++j) run[j] = run[j - 1] + (((mask >> (j - 1)) & 1) ? 0 : 1);
+        T->start.push_back((int32_t)(T->perm.size() / m));
+        std::vector<int> pi(m);
+        for (int j = 0; j < m; ++j) pi[j] = j;
+        do {
+            bool keep = true;
+            for (int j = 0; j < m && keep; ++j) keep = run[pi[j]] == run[j];
+            if (keep)
+                for (int j = 0; j < m; ++j) T->perm.push_back((uint8_t)pi[j]);
+        } while (std::next_permutation(pi.begin(), pi.end()));
+    }
+    T->start.push_back((int32_t)(T->perm.size() / m));
+    if (!upload(T->start, &T->d_start, err) || !upload(T->perm, &T->d_perm, err)) return nullptr;
+    const StabTable *out = T.get();
+    g_stab.emplace(std::make_pair(dev, m), std::move(T));
+    return out;
+}
+
 }  // namespace symt

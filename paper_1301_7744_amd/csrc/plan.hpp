@@ -105,4 +105,18 @@ struct MetaTable {
 };
 const MetaTable *meta_get(int m, int nbar, int b, std::string *err);
 
+// Stabilisers of sorted block tuples of order m: a sorted tuple's equal
+// entries form runs of consecutive positions; bit j of its run mask is set
+// when s_j == s_{j+1}.  The permutations of the m positions that map every
+// run onto itself (the tuple's stabiliser) for mask x are
+// perm[start[x]*m .. start[x+1]*m), m positions each, identity first.
+struct StabTable {
+    int m = 0;
+    std::vector<int32_t> start;   // 2^(m-1) + 1
+    std::vector<uint8_t> perm;
+    int32_t *d_start = nullptr;
+    uint8_t *d_perm = nullptr;
+};
+const StabTable *stab_get(int m, std::string *err);
+
 }  // namespace symt

@@ -66,10 +66,14 @@ template <int M, int B, int K, int NT, int KT>
 struct Bf16Cfg {
     static constexpr int MT = B * B;
     static constexpr bool KM = K == 0;                  // LDS [row][kk] (else [kk][row])
+    // One block per chunk (b = 16, K chunk 16) below the last level: a
+    // chunk whose block has its contracted mode stored fastest (q = 0) is
+    // staged as [row][kk] instead, so no entry is ever written transposed.
+    static constexpr bool DUAL = !KM && KT == B;
     static constexpr int RS = MT + 16;                  // [kk][row] row stride (bf16)
     static constexpr int RSK = KT + 8;                  // [row][kk] row stride
     static constexpr int XS = KT + 8;                   // X [nn][kk] row stride
-    static constexpr int IN_ELEMS = KM ? MT * RSK : KT * RS;
+    static constexpr int IN_ELEMS = KM ? MT * RSK : (DUAL ? (KT * RS > MT * RSK ? KT * RS : MT * RSK) : KT * RS);
     // waves along M: 4 for 32-wide column tiles, else 2 (1 for 64-row tiles)
     static constexpr int WM = NT <= 32 ? 4 : (MT >= 128 ? 2 : 1), WN = 4 / WM;
     static constexpr int WTM = MT / WM, WTN = NT / WN;
@@ -133,7 +137,7 @@ __device__ __forceinline__ void place(int d0, int d1, int d2, const int *fixed_d
     const int row = r0 + B * r1;
     if constexpr (KM) *loff = row * RSK + kbase + dk;
     else *loff = (kbase + dk) * RS + row;
-    *along_k = pk == 0;
+    *along_k = !KM && pk == 0;
 }
 
 template <int M, int B, int K, int NT, int KT, int PD>
@@ -198,6 +202,7 @@ __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, B
     u32x4 rin[PD][NV], rx[PD][NXV];
     int rl[PD][NV];
     bool rk[PD][NV], rv[PD][NV], rxv[PD][NXV];
+    bool rkm[PD];   // DUAL: the chunk's block is staged [row][kk]
     auto load_chunk = [&](int c, int u) {
 #pragma unroll
         for (int f = 0; f < NV; ++f) {
@@ -214,7 +219,8 @@ __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, B
             switch (q) {
 #define STTSM_Q(QQ) \
     case QQ: \
-        if constexpr (QQ <= K) place<M, B, K, QQ, RS, RSK, C::KM>(vd0[f], vd1[f], vd2[f], fixed, kb, &goff, &loff, &ak); \
+        if constexpr (QQ <= K) \
+            place<M, B, K, QQ, RS, RSK, C::KM || (C::DUAL && QQ == 0)>(vd0[f], vd1[f], vd2[f], fixed, kb, &goff, &loff, &ak); \
         break;
                 STTSM_Q(0) STTSM_Q(1) STTSM_Q(2) STTSM_Q(3)
 #undef STTSM_Q
@@ -223,6 +229,7 @@ __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, B
             rl[u][f] = loff;
             rk[u][f] = ak;
             rv[u][f] = valid;
+            if (f == 0) rkm[u] = C::DUAL && q == 0;
             rin[u][f] = *(const u32x4 *)(in + sm.s_ioff[ibc] + goff);
         }
 #pragma unroll
@@ -281,6 +288,7 @@ __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, B
     auto mfma_chunk = [&](int buf, int c, int u) {
         const u16 *si = sm.s_in[buf];
         const u16 *sx = sm.s_x[buf];
+        const bool km = C::KM || (C::DUAL && rkm[u]);   // read before stage u is reloaded
 #pragma unroll
         for (int s = 0; s < KT / 16; ++s) {
             bf16x8 va[TM], vb[TN];
@@ -288,7 +296,7 @@ __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, B
 #pragma unroll
                 for (int i = 0; i < TM; ++i) {
                     const int rb = wm * WTM + 32 * i;
-                    if constexpr (C::KM) {
+                    if (km) {
                         va[i] = __builtin_bit_cast(bf16x8, *(const u16x8 *)&si[(rb + r32) * RSK + 16 * s + 8 * half]);
                     } else {
                         // Lane 4t + u of a 16-lane group points at row kk0 + t,
@@ -436,12 +444,12 @@ __global__ __launch_bounds__(256, 2) void grouped_fast_bf16(const StageArgs *__r
 // Default tile (NT, KT, PD) per block size; the grouped kernel always uses it.
 template <int B>
 struct Bf16Default {
-    static constexpr int NT = B == 16 ? 64 : 128, KT = 32, PD = 1;
+    static constexpr int NT = B == 16 ? 64 : 128, KT = 16, PD = 2;
 };
 
 // Other per-level tiles (NT, KT, PD), selectable for measurement.
-#define STTSM_BF16_TILES_16(X) X(128, 32, 1) X(64, 32, 2) X(64, 16, 2) X(128, 16, 2) X(32, 16, 1) X(32, 16, 2) X(32, 32, 1) X(32, 32, 2)
-#define STTSM_BF16_TILES_8(X) X(256, 32, 1) X(128, 32, 2) X(128, 16, 2) X(128, 16, 3)
+#define STTSM_BF16_TILES_16(X) X(128, 32, 1) X(64, 32, 1) X(64, 32, 2) X(64, 16, 1) X(64, 16, 3) X(128, 16, 2) X(32, 16, 1)
+#define STTSM_BF16_TILES_8(X) X(256, 32, 1) X(128, 32, 1) X(128, 32, 2) X(128, 16, 3)
 
 template <int M, int B, int K>
 int launch_one(const StageArgs &a, int NT, int KT, int PD, const StageArgs *d_stages, const GroupedTask *d_tasks,

@@ -354,9 +354,9 @@ def bf16_fast_level0_tasks(m, n, p, b):
     override = os.environ.get("STTSM_BF16_TILE", "")   # "NTxKTxPD", a measurement override
     if override and "," not in override:
         o_nt = int(override.split("x")[0])
-        if (b == 16 and override in ("128x32x1", "64x32x2", "64x16x2", "128x16x2", "32x16x1", "32x16x2", "32x32x1",
-                                       "32x32x2")) or \
-                (b == 8 and override in ("256x32x1", "128x32x2", "128x16x2", "128x16x3")):
+        if (b == 16 and override in ("128x32x1", "64x32x1", "64x32x2", "64x16x1", "64x16x3", "128x16x2",
+                                       "32x16x1")) or \
+                (b == 8 and override in ("256x32x1", "128x32x1", "128x32x2", "128x16x3")):
             nt = o_nt
     return comb(nbar + m - 2, m - 1) * (-(-(pbar * b) // nt)) * b ** (m - 3)
 
@@ -439,3 +439,57 @@ def test_all_but_one_vs_oracle(case):
     say("  rel err", e, "bound", bound)
     assert got.shape == ref.shape
     assert e <= bound
+
+
+# ------------------------------------------------------------------ symmetrisation
+@pytest.mark.parametrize("m,n,b,dt", [(2, 7, 3, "f32"), (3, 10, 4, "f32"), (4, 9, 2, "f32"), (3, 16, 4, "f64"),
+                                      (3, 40, 8, "bf16"), (5, 6, 2, "f32")])
+def test_symmetrize_vs_oracle(m, n, b, dt):
+    """bcss_symmetrize on a BCSS array that is not symmetric inside its
+    blocks: equal to the oracle (dense average over all m! permutations,
+    packed), mirrored entries bitwise equal, blocks without repeated block
+    indices untouched."""
+    import itertools
+    import torch
+    tdt = {"f32": torch.float32, "f64": torch.float64, "bf16": torch.bfloat16}[dt]
+    nb = st().bcss_num_blocks(m, -(-n // b))
+    raw = synth.rng((m, n, b, 81)).standard_normal((nb, b ** m))
+    X = bcss_ref.pack(bcss_ref.unpack(raw, m, n, b), b)       # zero padding
+    if dt == "bf16":
+        X = synth.round_to_bf16(X.astype(np.float32)).astype(np.float64)
+    dev = torch.from_numpy(X.ravel()).to(tdt).cuda()
+    X = dev.double().cpu().numpy().reshape(nb, b ** m)          # the values the GPU holds
+    st().bcss_symmetrize(dev, m, n, b)
+    torch.cuda.synchronize()
+    got = dev.double().cpu().numpy().reshape(nb, b ** m)
+    ref = bcss_ref.symmetrize(X, m, n, b)
+    tol = {"f32": 1e-6, "f64": 1e-14, "bf16": 2 ** -8}[dt]
+    say("symmetrize", m, n, b, dt, "max diff", np.abs(got - ref).max())
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+    D = bcss_ref.unpack(got, m, n, b)
+    for p in itertools.permutations(range(m)):
+        assert np.array_equal(np.transpose(D, p), D)
+    for r, s in enumerate(bcss_ref.sorted_block_tuples(m, -(-n // b))):
+        if len(set(s)) == m:
+            assert np.array_equal(got[r], X[r])
+
+
+def test_symmetrize_after_sttsm():
+    """C from sttsm, symmetrised: exactly symmetric, still within the FP32
+    bound of the oracle."""
+    import itertools
+    import torch
+    m, n, p, b = 3, 35, 20, 8
+    A = synth.symmetric_uniform(m, n, 91)
+    X = synth.change_of_basis(p, n, 92)
+    Ab = st().bcss_pack(dev_dense(A), m, n, b)
+    Xd = torch.from_numpy(X).cuda()
+    C, _ = st().sttsm(Ab, Xd, m, n, p, b, b, P32)
+    st().bcss_symmetrize(C, m, p, b)
+    torch.cuda.synchronize()
+    nb = st().bcss_num_blocks(m, -(-p // b))
+    got = C.double().cpu().numpy().reshape(nb, b ** m)
+    D = bcss_ref.unpack(got, m, p, b)
+    for q in itertools.permutations(range(m)):
+        assert np.array_equal(np.transpose(D, q), D)
+    assert err(got, ref_bcss(A.astype(np.float64), X.astype(np.float64), b), m, p, b) <= TOL_FP32

@@ -181,3 +181,34 @@ def test_limit_approximation_of_table3():
         ratios.append(costs.flops_dense(m, n, n) / exact)
     assert gaps == sorted(gaps, reverse=True) and gaps[-1] < 1.04
     assert ratios == sorted(ratios)
+
+
+# ------------------------------------------------------------------ symmetrisation (end of §5.4)
+def test_symmetrize_matrix_case():
+    """m = 2: a diagonal block becomes (M + M^T)/2, other blocks are kept."""
+    m, n, b = 2, 6, 3
+    tuples = bcss_ref.sorted_block_tuples(m, 2)
+    X = synth.rng(5).standard_normal((len(tuples), b * b))
+    Y = bcss_ref.symmetrize(X, m, n, b)
+    for r, s in enumerate(tuples):
+        M = X[r].reshape(b, b, order="F")
+        want = (M + M.T) / 2 if s[0] == s[1] else M
+        assert np.allclose(Y[r].reshape(b, b, order="F"), want, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("m,n,b", [(3, 6, 2), (3, 7, 3), (4, 5, 2)])
+def test_symmetrize_invariants(m, n, b):
+    """Output is a symmetric tensor; symmetrising twice changes nothing; an
+    exactly symmetric input is returned (to rounding); the sum over every
+    dense permutation orbit is kept."""
+    nb = len(bcss_ref.sorted_block_tuples(m, -(-n // b)))
+    X = synth.rng((m, n, b)).standard_normal((nb, b ** m))
+    Y = bcss_ref.symmetrize(X, m, n, b)
+    D = bcss_ref.unpack(Y, m, n, b)
+    for p in itertools.permutations(range(m)):
+        assert np.allclose(np.transpose(D, p), D, rtol=0, atol=1e-14)
+    assert np.allclose(bcss_ref.symmetrize(Y, m, n, b), Y, rtol=0, atol=1e-14)
+    A = synth.symmetric_uniform(m, n, (m, n, 3)).astype(np.float64)
+    P = bcss_ref.pack(A, b)
+    assert np.allclose(bcss_ref.symmetrize(P, m, n, b), P, rtol=0, atol=1e-15)
+    assert abs(bcss_ref.unpack(X, m, n, b).sum() - D.sum()) <= 1e-10 * np.abs(D).sum()
