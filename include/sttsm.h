@@ -248,7 +248,11 @@ int sttsm_server_create(void *arena, size_t arena_bytes, int32_t max_inflight, s
 size_t sttsm_request_footprint(const sttsm_request *req);
 
 /* Queues a request; never waits for the GPU.  EINVAL for a bad request,
- * ENOMEM when its footprint exceeds the whole arena (it could never run). */
+ * ENOMEM when its footprint exceeds the whole arena (it could never run).
+ * The server copies A_bcss and X on its own stream some time after the call
+ * returns and does not wait for work the caller queued elsewhere: their
+ * values must be final (the producing stream synchronised) before the call,
+ * and they must stay valid until the request is fetched. */
 int sttsm_submit(sttsm_server *s, const sttsm_request *req, uint64_t *ticket);
 
 /* *state <- STTSM_QUEUED .. STTSM_FAILED; ENOTFOUND for an unknown ticket. */

@@ -352,7 +352,12 @@ class Server:
         self._keep = {}
 
     def submit(self, A_bcss, X, m: int, n: int, p: int, bA: int, bC: int, prec: int) -> int:
+        """Queues a request.  Work the caller queued on its current stream
+        (for example the kernels that produced A and X) is finished first:
+        the server reads the inputs on its own stream."""
+        import torch
         req = make_request(A_bcss, X, m, n, p, bA, bC, prec)
+        torch.cuda.current_stream().synchronize()
         t = ctypes.c_uint64()
         _check(load().sttsm_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
         self._keep[t.value] = (A_bcss, X, m, p, bC)   # inputs stay alive until fetched

@@ -4,9 +4,11 @@
 // arrival order while their footprint fits in the arena and the in-flight
 // cap allows, (2) stages the inputs and index tables of newly admitted
 // requests into their arena regions and builds their padded X panels, and
-// (3) runs the next level of every active request in grouped persistent
+// (3) queues the next level of every active request in grouped persistent
 // launches (one per kernel class present) whose workgroups take tiles of all
-// requests from one shared queue.  Completion of the last level marks a
+// requests from one shared queue.  Rounds are double buffered: round r + 1 is
+// formed and queued on the stream while round r runs (the stream orders each
+// request's levels), and the worker only then waits for round r.  Completion of the last level marks a
 // request done; its A, X, temporaries and tables are released at once and
 // its C when the caller fetches it.
 #include <hip/hip_runtime.h>
@@ -103,7 +105,7 @@ struct Req {
     Footprint fp;
     size_t off_main = 0, off_c = 0;
     char *main = nullptr, *C = nullptr;
-    int level = -1;            // next level to run; m when done
+    int level = 0;             // next level to enqueue; m once the last is enqueued
     double t_submit = 0, t_done = 0;
 };
 
@@ -149,15 +151,22 @@ struct sttsm_server {
     uint64_t next_ticket = 1;
     bool stop = false;
     std::string fatal;
-    // device side of the rounds
+    // device side of the rounds: two slots, so that the next round is formed
+    // and queued while the previous one runs
     hipStream_t stream = nullptr;
-    hipEvent_t ev = nullptr;
-    StageArgs *d_stages = nullptr;
-    GroupedTask *d_tasks = nullptr;
-    int *d_heads = nullptr;
-    size_t cap_stages = 0, cap_tasks = 0;
-    StageArgs *h_stages = nullptr;   // pinned staging
-    GroupedTask *h_tasks = nullptr;
+    struct Slot {
+        hipEvent_t ev = nullptr;
+        StageArgs *d_stages = nullptr;
+        GroupedTask *d_tasks = nullptr;
+        int *d_heads = nullptr;
+        size_t cap_stages = 0, cap_tasks = 0;
+        StageArgs *h_stages = nullptr;   // pinned staging
+        GroupedTask *h_tasks = nullptr;
+        bool pending = false;            // queued, not yet completed
+        int launches = 0;
+        std::vector<Req *> members;      // requests with a level in this round
+        std::vector<Req *> finishing;    // ... whose last level it is
+    } slot[2];
     // statistics
     std::vector<double> lat_us;
     double t_first_submit = -1, t_last_done = 0;
@@ -167,7 +176,7 @@ struct sttsm_server {
 
 namespace {
 
-bool ensure_capacity(sttsm_server *S, size_t nstages, size_t ntasks, std::string *err)
+bool ensure_capacity(sttsm_server::Slot *S, size_t nstages, size_t ntasks, std::string *err)
 {
     if (nstages > S->cap_stages) {
         const size_t cap = std::max(nstages, 2 * S->cap_stages);
@@ -290,63 +299,119 @@ void fail_active(sttsm_server *S, const std::string &why)
         release_c(S, q);
     }
     S->active.clear();
+    for (auto &sl : S->slot) {
+        for (Req *q : sl.finishing) {
+            q->state = STTSM_FAILED;
+            release_main(S, q);
+            release_c(S, q);
+        }
+        sl.finishing.clear();
+        sl.members.clear();
+        sl.pending = false;
+    }
     S->fatal = why;
     S->cv_done.notify_all();
+}
+
+// Waits for a queued round and retires it: requests whose last level ran in
+// it are done (their inputs, temporaries and tables are released; C stays
+// until fetched).  Called with the lock not held.
+bool complete_round(sttsm_server *S, sttsm_server::Slot &sl, std::string *err)
+{
+    const hipError_t e = hipEventSynchronize(sl.ev);
+    std::lock_guard<std::mutex> lk(S->mu);
+    sl.pending = false;
+    if (e != hipSuccess) {
+        *err = std::string("server: round failed: ") + hipGetErrorString(e);
+        return false;
+    }
+    ++S->rounds;
+    S->launches += sl.launches;
+    const double t = now_us();
+    for (Req *q : sl.finishing) {
+        q->state = STTSM_DONE;
+        q->t_done = t;
+        release_main(S, q);
+        S->lat_us.push_back(t - q->t_submit);
+        S->t_last_done = t;
+    }
+    sl.finishing.clear();
+    sl.members.clear();
+    S->cv_done.notify_all();
+    S->cv_work.notify_one();   // freed arena may admit waiting requests
+    return true;
 }
 
 void worker_loop(sttsm_server *S)
 {
     (void)hipSetDevice(S->device);
     std::string err;
+    int cur = 0;   // slot of the round being formed; slot cur ^ 1 may be in flight
     for (;;) {
         std::vector<Req *> fresh, active;
+        bool stopping = false;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            S->cv_work.wait(lk, [&] { return S->stop || !S->arrival.empty() || !S->active.empty(); });
-            if (S->stop) {
-                for (Req *q : S->arrival) q->state = STTSM_FAILED;
-                S->arrival.clear();
-                fail_active(S, "server stopped");
-                return;
-            }
-            // Admission: first come, first served, within the arena and the cap.
-            while (!S->arrival.empty() && (int)S->active.size() < S->max_inflight) {
-                Req *q = S->arrival.front();
-                size_t om = 0, oc = 0;
-                if (!S->alloc.alloc(q->fp.main, &om)) break;
-                if (!S->alloc.alloc(q->fp.c, &oc)) {
-                    S->alloc.release(om, q->fp.main);
-                    break;
+            S->cv_work.wait(lk, [&] {
+                return S->stop || !S->arrival.empty() || !S->active.empty() || S->slot[cur ^ 1].pending;
+            });
+            stopping = S->stop;
+            if (!stopping) {
+                // Admission: first come, first served, within the arena and the cap.
+                while (!S->arrival.empty() && (int)S->active.size() < S->max_inflight) {
+                    Req *q = S->arrival.front();
+                    size_t om = 0, oc = 0;
+                    if (!S->alloc.alloc(q->fp.main, &om)) break;
+                    if (!S->alloc.alloc(q->fp.c, &oc)) {
+                        S->alloc.release(om, q->fp.main);
+                        break;
+                    }
+                    q->off_main = om;
+                    q->off_c = oc;
+                    q->main = S->arena + om;
+                    q->C = S->arena + oc;
+                    q->state = STTSM_ADMITTED;
+                    S->arrival.pop_front();
+                    S->active.push_back(q);
+                    fresh.push_back(q);
                 }
-                q->off_main = om;
-                q->off_c = oc;
-                q->main = S->arena + om;
-                q->C = S->arena + oc;
-                q->state = STTSM_ADMITTED;
-                S->arrival.pop_front();
-                S->active.push_back(q);
-                fresh.push_back(q);
+                active = S->active;
             }
-            active = S->active;
+        }
+        if (stopping) {
+            // let queued rounds finish before their memory is given back
+            for (auto &sl : S->slot)
+                if (sl.pending) (void)hipEventSynchronize(sl.ev);
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (Req *q : S->arrival) q->state = STTSM_FAILED;
+            S->arrival.clear();
+            fail_active(S, "server stopped");
+            return;
         }
         if (active.empty()) {
+            if (S->slot[cur ^ 1].pending) {
+                if (!complete_round(S, S->slot[cur ^ 1], &err)) {
+                    std::lock_guard<std::mutex> lk(S->mu);
+                    fail_active(S, err);
+                }
+                continue;
+            }
             // nothing fits yet although requests wait: a finished C is
             // holding the arena until fetched; sleep until something changes
             std::unique_lock<std::mutex> lk(S->mu);
             S->cv_work.wait_for(lk, std::chrono::milliseconds(2));
             continue;
         }
+        sttsm_server::Slot &sl = S->slot[cur];
         bool ok = true;
         for (Req *q : fresh)
             if (!stage_inputs(S, q, &err)) { ok = false; break; }
-        // Next level of every active request, grouped by compute form.
+        // Next level of every active request.  The stream orders it after the
+        // request's previous level, which may still be running.
         size_t nst = active.size(), ntk = 0;
-        for (Req *q : active) {
-            if (q->level < 0) q->level = 0;
-            ntk += q->plan->stages[q->level].tasks.size();
-        }
-        if (ok) ok = ensure_capacity(S, nst, ntk, &err);
-        int nl = 0;
+        for (Req *q : active) ntk += q->plan->stages[q->level].tasks.size();
+        if (ok) ok = ensure_capacity(&sl, nst, ntk, &err);
+        sl.launches = 0;
         if (ok) {
             // One launch per kernel class: the generic grouped kernel per
             // compute form, and the block-copy bf16 kernel per (m, b, k).
@@ -359,65 +424,65 @@ void worker_loop(sttsm_server *S)
                     const Req *q = active[i];
                     const StagePlan &St = q->plan->stages[q->level];
                     if (launch_class(q->plan->m, q->plan->bA, St) != cls) continue;
-                    S->h_stages[i] = stage_args_for(q, q->level);
-                    for (const Task &t : St.tasks) S->h_tasks[ti++] = GroupedTask{(int32_t)i, t.group, t.mt, t.nt};
+                    sl.h_stages[i] = stage_args_for(q, q->level);
+                    for (const Task &t : St.tasks) sl.h_tasks[ti++] = GroupedTask{(int32_t)i, t.group, t.mt, t.nt};
                     cls_m[cls] = q->plan->m;
                     cls_b[cls] = q->plan->bA;
                     cls_k[cls] = St.k;
                 }
                 cls_cnt[cls] = ti - cls_t0[cls];
             }
-            if (hipMemcpyAsync(S->d_stages, S->h_stages, nst * sizeof(StageArgs), hipMemcpyHostToDevice, S->stream) !=
+            if (hipMemcpyAsync(sl.d_stages, sl.h_stages, nst * sizeof(StageArgs), hipMemcpyHostToDevice,
+                               S->stream) != hipSuccess ||
+                hipMemcpyAsync(sl.d_tasks, sl.h_tasks, ntk * sizeof(GroupedTask), hipMemcpyHostToDevice, S->stream) !=
                     hipSuccess ||
-                hipMemcpyAsync(S->d_tasks, S->h_tasks, ntk * sizeof(GroupedTask), hipMemcpyHostToDevice, S->stream) !=
-                    hipSuccess ||
-                hipMemsetAsync(S->d_heads, 0, kLaunchClasses * sizeof(int), S->stream) != hipSuccess) {
+                hipMemsetAsync(sl.d_heads, 0, kLaunchClasses * sizeof(int), S->stream) != hipSuccess) {
                 ok = false;
                 err = "server: upload of the round failed";
             }
             for (int cls = 0; cls < kLaunchClasses && ok; ++cls) {
                 if (!cls_cnt[cls]) continue;
                 const int cnt = (int)cls_cnt[cls];
-                const GroupedTask *tk = S->d_tasks + cls_t0[cls];
-                int *head = S->d_heads + cls;
+                const GroupedTask *tk = sl.d_tasks + cls_t0[cls];
+                int *head = sl.d_heads + cls;
                 const int rc = cls < CMP_X3 + 1
-                                   ? launch_grouped(cls, S->d_stages, tk, cnt, head, S->grid, S->stream)
-                                   : launch_grouped_bf16(cls_m[cls], cls_b[cls], cls_k[cls], S->d_stages, tk, cnt,
+                                   ? launch_grouped(cls, sl.d_stages, tk, cnt, head, S->grid, S->stream)
+                                   : launch_grouped_bf16(cls_m[cls], cls_b[cls], cls_k[cls], sl.d_stages, tk, cnt,
                                                          head, S->grid, S->stream);
                 if (rc) {
                     ok = false;
                     err = "server: grouped launch failed";
                 }
-                ++nl;
+                ++sl.launches;
             }
         }
-        if (ok && (hipEventRecord(S->ev, S->stream) != hipSuccess || hipEventSynchronize(S->ev) != hipSuccess)) {
+        if (ok && hipEventRecord(sl.ev, S->stream) != hipSuccess) {
             ok = false;
-            err = std::string("server: round failed: ") + hipGetErrorString(hipGetLastError());
+            err = std::string("server: event record failed: ") + hipGetErrorString(hipGetLastError());
         }
-        std::lock_guard<std::mutex> lk(S->mu);
-        if (!ok) {
-            fail_active(S, err);
-            continue;
-        }
-        ++S->rounds;
-        S->launches += nl;
-        const double t = now_us();
-        std::vector<Req *> still;
-        for (Req *q : active) {
-            q->state = STTSM_RUNNING;
-            if (++q->level == q->r.A.m) {
-                q->state = STTSM_DONE;
-                q->t_done = t;
-                release_main(S, q);
-                S->lat_us.push_back(t - q->t_submit);
-                S->t_last_done = t;
-            } else {
-                still.push_back(q);
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (!ok) {
+                fail_active(S, err);
+                continue;
             }
+            sl.pending = true;
+            sl.members = active;
+            std::vector<Req *> still;
+            for (Req *q : active) {
+                q->state = STTSM_RUNNING;
+                if (++q->level == q->r.A.m) sl.finishing.push_back(q);
+                else still.push_back(q);
+            }
+            S->active.swap(still);
         }
-        S->active.swap(still);
-        S->cv_done.notify_all();
+        // The previous round completes while this one is queued behind it.
+        sttsm_server::Slot &prev = S->slot[cur ^ 1];
+        if (prev.pending && !complete_round(S, prev, &err)) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            fail_active(S, err);
+        }
+        cur ^= 1;
     }
 }
 
@@ -458,11 +523,16 @@ int sttsm_server_create(void *arena, size_t arena_bytes, int32_t max_inflight, s
         S->grid = 2 * cus;
     if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess)
         return fail(STTSM_EHIP, "hipStreamCreate failed");
-    if (hipEventCreateWithFlags(&S->ev, hipEventDisableTiming) != hipSuccess ||
-        hipMalloc((void **)&S->d_heads, kLaunchClasses * sizeof(int)) != hipSuccess) {
-        (void)hipStreamDestroy(S->stream);
-        return fail(STTSM_EHIP, "server: cannot create event or queue heads");
-    }
+    for (auto &sl : S->slot)
+        if (hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess ||
+            hipMalloc((void **)&sl.d_heads, kLaunchClasses * sizeof(int)) != hipSuccess) {
+            for (auto &s2 : S->slot) {
+                if (s2.ev) (void)hipEventDestroy(s2.ev);
+                if (s2.d_heads) (void)hipFree(s2.d_heads);
+            }
+            (void)hipStreamDestroy(S->stream);
+            return fail(STTSM_EHIP, "server: cannot create event or queue heads");
+        }
     sttsm_server *raw = S.release();
     raw->worker = std::thread(worker_loop, raw);
     *out = raw;
@@ -582,12 +652,14 @@ int sttsm_server_destroy(sttsm_server *S)
     S->cv_work.notify_all();
     if (S->worker.joinable()) S->worker.join();
     (void)hipStreamSynchronize(S->stream);
-    if (S->d_stages) (void)hipFree(S->d_stages);
-    if (S->d_tasks) (void)hipFree(S->d_tasks);
-    if (S->d_heads) (void)hipFree(S->d_heads);
-    if (S->h_stages) (void)hipHostFree(S->h_stages);
-    if (S->h_tasks) (void)hipHostFree(S->h_tasks);
-    (void)hipEventDestroy(S->ev);
+    for (auto &sl : S->slot) {
+        if (sl.d_stages) (void)hipFree(sl.d_stages);
+        if (sl.d_tasks) (void)hipFree(sl.d_tasks);
+        if (sl.d_heads) (void)hipFree(sl.d_heads);
+        if (sl.h_stages) (void)hipHostFree(sl.h_stages);
+        if (sl.h_tasks) (void)hipHostFree(sl.h_tasks);
+        (void)hipEventDestroy(sl.ev);
+    }
     (void)hipStreamDestroy(S->stream);
     delete S;
     return STTSM_OK;
