@@ -121,17 +121,24 @@ def serve_bench(args):
         t0 = time.perf_counter()
 
         def drain(block):
+            """Fetch every finished request (any order); with block, wait
+            until at least one has finished."""
             while pending:
-                t, rid = pending[0]
-                st_ = srv.wait(t, -1.0 if block else 0.0)
-                if st_ not in (st.DONE, st.FAILED):
+                done = []
+                for t, rid in pending:
+                    st_ = srv.poll(t)
+                    if st_ == st.FAILED:
+                        raise RuntimeError("served request failed")
+                    if st_ == st.DONE:
+                        done.append((t, rid))
+                for t, rid in done:
+                    C = srv.fetch(t)
+                    if rid in sample_ids:
+                        kept[rid] = C.cpu()
+                    pending.remove((t, rid))
+                if done or not block:
                     return
-                if st_ == st.FAILED:
-                    raise RuntimeError("served request failed")
-                C = srv.fetch(t)
-                if rid in sample_ids:
-                    kept[rid] = C.cpu()
-                pending.pop(0)
+                time.sleep(0.00005)
 
         for i, r in enumerate(shapes):
             if arrivals is not None:

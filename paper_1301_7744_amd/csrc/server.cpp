@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -168,6 +170,7 @@ struct sttsm_server {
         std::vector<Req *> finishing;    // ... whose last level it is
     } slot[2];
     // statistics
+    double t_stage_us = 0, t_form_us = 0, t_queue_us = 0, t_wait_us = 0;   // worker host time by phase
     std::vector<double> lat_us;
     double t_first_submit = -1, t_last_done = 0;
     int64_t rounds = 0, launches = 0;
@@ -318,8 +321,10 @@ void fail_active(sttsm_server *S, const std::string &why)
 // until fetched).  Called with the lock not held.
 bool complete_round(sttsm_server *S, sttsm_server::Slot &sl, std::string *err)
 {
+    const double t0 = now_us();
     const hipError_t e = hipEventSynchronize(sl.ev);
     std::lock_guard<std::mutex> lk(S->mu);
+    S->t_wait_us += now_us() - t0;
     sl.pending = false;
     if (e != hipSuccess) {
         *err = std::string("server: round failed: ") + hipGetErrorString(e);
@@ -404,8 +409,10 @@ void worker_loop(sttsm_server *S)
         }
         sttsm_server::Slot &sl = S->slot[cur];
         bool ok = true;
+        const double t_a = now_us();
         for (Req *q : fresh)
             if (!stage_inputs(S, q, &err)) { ok = false; break; }
+        const double t_b = now_us();
         // Next level of every active request.  The stream orders it after the
         // request's previous level, which may still be running.
         size_t nst = active.size(), ntk = 0;
@@ -432,6 +439,7 @@ void worker_loop(sttsm_server *S)
                 }
                 cls_cnt[cls] = ti - cls_t0[cls];
             }
+            S->t_form_us += now_us() - t_b;
             if (hipMemcpyAsync(sl.d_stages, sl.h_stages, nst * sizeof(StageArgs), hipMemcpyHostToDevice,
                                S->stream) != hipSuccess ||
                 hipMemcpyAsync(sl.d_tasks, sl.h_tasks, ntk * sizeof(GroupedTask), hipMemcpyHostToDevice, S->stream) !=
@@ -460,6 +468,8 @@ void worker_loop(sttsm_server *S)
             ok = false;
             err = std::string("server: event record failed: ") + hipGetErrorString(hipGetLastError());
         }
+        S->t_stage_us += t_b - t_a;
+        S->t_queue_us += now_us() - t_a - (t_b - t_a);
         {
             std::lock_guard<std::mutex> lk(S->mu);
             if (!ok) {
@@ -651,6 +661,10 @@ int sttsm_server_destroy(sttsm_server *S)
     }
     S->cv_work.notify_all();
     if (S->worker.joinable()) S->worker.join();
+    if (getenv("STTSM_SERVER_TIMING"))
+        fprintf(stderr, "sttsm server: %lld rounds; worker ms: staging inputs %.1f, forming rounds %.1f, "
+                        "forming+queueing %.1f, waiting %.1f\n", (long long)S->rounds, S->t_stage_us * 1e-3,
+                S->t_form_us * 1e-3, S->t_queue_us * 1e-3, S->t_wait_us * 1e-3);
     (void)hipStreamSynchronize(S->stream);
     for (auto &sl : S->slot) {
         if (sl.d_stages) (void)hipFree(sl.d_stages);
