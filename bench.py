@@ -22,6 +22,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "bf16x3_fp32": 2500.0, "bf16x3_bf16": 2500.0}
 PEAK_HBM_GBS = 8000.0
+# fp32 FMA on the vector ALUs without packed instructions: 256 CUs x 4 SIMD x
+# 16 lanes x 2 flop x 2.4 GHz (packed fp32 would double it; it is disabled).
+PEAK_VALU_FP32_TFLOPS = 78.6
 
 
 def measured_traffic(workload, prec, level):
@@ -68,8 +71,9 @@ def parse():
     ap.add_argument("--workload", default="m3_n256_b16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
-    ap.add_argument("--op", default="sttsm", choices=["sttsm", "all_but_one"],
-                    help="sttsm, or the product in all modes but mode 0")
+    ap.add_argument("--op", default="sttsm", choices=["sttsm", "all_but_one", "vectors"],
+                    help="sttsm, the product in all modes but mode 0, or batched vector products")
+    ap.add_argument("--vectors", type=int, default=64, help="batch size V of --op vectors")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum oracle time for the CPU baseline")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="before timing, copy this many MiB device to device once (a plain copy kernel of known "
@@ -245,6 +249,81 @@ def serve_bench(args):
     print(json.dumps(res), flush=True)
 
 
+def vectors_bench(args):
+    """Batched y_v = A x_v^(m-1), s_v = A x_v^m on a named workload's A."""
+    import numpy as np
+    import torch
+    import paper_1301_7744_amd as st
+    import synth
+    cfg = synth.CONFIGS[args.workload]
+    m, n, b, V = cfg["m"], cfg["n"], cfg["bA"], args.vectors
+    dev = torch.device("cuda:0")
+    A_np, _ = synth.make_config_inputs(args.workload)
+    X_np = synth.rng((n, V, 97)).standard_normal((V, n)).astype(np.float32) / np.sqrt(n)
+    tdt = torch.float32
+    if args.prec == "bf16":
+        A_np, X_np, tdt = synth.round_to_bf16(A_np), synth.round_to_bf16(X_np), torch.bfloat16
+    A = st.bcss_pack(torch.from_numpy(np.ascontiguousarray(A_np.ravel(order="F"))).to(tdt).to(dev), m, n, b)
+    X = torch.from_numpy(X_np).to(tdt).to(dev)
+    y, s, ws = st.sttsm_vectors(A, X, m, n, b)
+    call = lambda: st.sttsm_vectors(A, X, m, n, b, y=y, s=s, ws=ws)
+    for _ in range(args.warmup):
+        call()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        call()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        call()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+    ms = timed(graph.replay)
+    ms_eager = timed(call)
+    flops = st.sttsm_vectors_flops(m, n, b, V)
+    esz = 2 if args.prec == "bf16" else 4
+    nbytes = st.bcss_num_elems(m, n, b) * esz + V * n * (esz + 4) + V * 4
+    t_alu = flops / (PEAK_VALU_FP32_TFLOPS * 1e12)
+    t_hbm = nbytes / (PEAK_HBM_GBS * 1e9)
+    if t_alu >= t_hbm:
+        roof = {"bound": "alu", "achieved": round(flops / (ms * 1e-3) / 1e12, 3), "peak": PEAK_VALU_FP32_TFLOPS,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": round(nbytes / (ms * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["traffic"] = None
+    roof["kernel"] = "vec_partial_kernel + vec_reduce_kernel (%.3f GFLOP, %.1f MB algorithmic per call)" % (
+        flops / 1e9, nbytes / 1e6)
+    out = {"metric": "batched vector products A x^(m-1), A x^m GFLOP/s (each stored term once)",
+           "value": round(flops / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16" if args.prec == "bf16" else "f32", "data": "synthetic",
+           "config": {"workload": args.workload + "_V%d" % V, "m": m, "n": n, "b": b, "vectors": V,
+                      "launch": "graph replay", "eager_ms_per_step": round(ms_eager, 5)},
+           "roofline": roof}
+    if not args.no_cpu_baseline:
+        import oracle
+        t = time.perf_counter()
+        Y, S = oracle.vectors(A_np.astype(np.float64), X_np.astype(np.float64))
+        t_cpu = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": round(flops / t_cpu / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": "full batch, dense FP64 mode products per vector, %.1f s" % t_cpu}
+        out["rel_err_vs_fp64"] = float("%.3e" % (np.linalg.norm(y.double().cpu().numpy() - Y) / np.linalg.norm(Y)))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -254,6 +333,8 @@ def main():
 
     if args.serve:
         return serve_bench(args)
+    if args.op == "vectors":
+        return vectors_bench(args)
 
     import numpy as np
     import torch

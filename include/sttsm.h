@@ -172,6 +172,29 @@ int sttsm_all_but_one(const bcss_layout *A, const void *A_dev, const void *X_dev
 int64_t sttsm_all_but_one_elems(const bcss_layout *A, const bcss_layout *C, int32_t prec);
 
 /*
+ * Batched vector products, the case of §2.5 where the matrix of sttsm is a
+ * single vector (as in the CP decomposition): for V vectors x_v,
+ *   y_v = A x_v^(m-1),  y_v[i] = sum_{i_2..i_m} a_{i i_2..i_m} x_v[i_2]...x_v[i_m],
+ *   s_v = A x_v^m = x_v . y_v.
+ * A   : BCSS, F32 or BF16, m >= 2, device.
+ * x   : V rows of n entries, row v at x + v*rs_x (A's dtype), device.
+ * y   : V rows of n fp32 entries, row v at y + v*rs_y, device, overwritten.
+ * s   : V fp32 entries, device, or NULL.
+ * ws  : device workspace of sttsm_vectors_workspace_bytes(A, V) bytes.
+ * Each stored block is read for every distinct block index it holds; the
+ * sums run in a fixed order (results are reproducible bit for bit); fp32
+ * accumulation.
+ */
+int sttsm_vectors(const bcss_layout *A, const void *A_dev, const void *x_dev, int64_t V, int64_t rs_x, float *y_dev,
+                  int64_t rs_y, float *s_dev, void *ws, size_t ws_bytes, void *stream);
+/* Workspace bytes for sttsm_vectors; 0 on bad arguments. */
+size_t sttsm_vectors_workspace_bytes(const bcss_layout *A, int64_t V);
+/* Multiply-add count x 2 of sttsm_vectors (every term once: per vector,
+ * b^m for each stored block and distinct block index in it); -1 on bad
+ * arguments. */
+int64_t sttsm_vectors_flops(const bcss_layout *A, int64_t V);
+
+/*
  * Where sttsm leaves temporary T^(k) (1 <= k <= m-1) inside the workspace.
  * T^(k) has extent n in modes 0..k-1 (symmetric, Theorem 1) and p in modes
  * k..m-1.  It is stored as [J][s][block]: J runs over sorted tuples

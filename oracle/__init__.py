@@ -168,3 +168,20 @@ def all_but_one(A: np.ndarray, X: np.ndarray) -> np.ndarray:
         T = mode_product(T, k, X)
     return T
 
+
+
+def vectors(A: np.ndarray, X: np.ndarray):
+    """The sttsm case of §2.5 where the matrix is one vector, for each row
+    x_v of X (V x n): y_v = A x_v^(m-1) (every mode but mode 0 multiplied by
+    x_v) and s_v = A x_v^m (every mode).  Returns (Y (V x n), s (V,)), FP64,
+    from the same dense mode products as all_but_one() and chain()."""
+    A = _as_dense_f64(A)
+    X = np.asarray(X, dtype=np.float64)
+    V, n = X.shape
+    Y = np.zeros((V, n))
+    s = np.zeros(V)
+    for v in range(V):
+        xv = X[v:v + 1, :]
+        Y[v] = all_but_one(A, xv).reshape(n, order="F")
+        s[v] = float(chain(A, xv).ravel()[0])
+    return Y, s

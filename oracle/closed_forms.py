@@ -47,3 +47,15 @@ def rank_r_all_but_one(lams, vecs, X: np.ndarray, m: int) -> np.ndarray:
         term = lam * np.multiply.outer(a64, outer_power(X64 @ a64, m - 1)) if m > 1 else lam * a64
         out = term if out is None else out + term
     return np.asfortranarray(out)
+
+
+def rank_r_vectors(lams, vecs, X: np.ndarray, m: int):
+    """For A = sum_i lam_i a_i^{o m} and rows x of X:
+    A x^(m-1) = sum_i lam_i (a_i . x)^(m-1) a_i and A x^m = sum_i lam_i (a_i . x)^m."""
+    X64 = np.asarray(X, dtype=np.float64)
+    Av = np.asarray(vecs, dtype=np.float64)          # r x n
+    dots = X64 @ Av.T                                  # V x r
+    lam = np.asarray(lams, dtype=np.float64)
+    Y = (dots ** (m - 1) * lam) @ Av
+    s = (dots ** m) @ lam
+    return Y, s

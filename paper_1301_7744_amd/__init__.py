@@ -64,6 +64,9 @@ def load():
         "sttsm_flops": (i64, [L, L]),
         "bcss_fill_hashed": (ctypes.c_int, [L, ctypes.c_uint64, ctypes.c_double, ctypes.c_double, vp, vp]),
         "bcss_symmetrize": (ctypes.c_int, [L, vp, vp]),
+        "sttsm_vectors": (ctypes.c_int, [L, vp, vp, i64, i64, vp, i64, vp, vp, sz, vp]),
+        "sttsm_vectors_workspace_bytes": (sz, [L, i64]),
+        "sttsm_vectors_flops": (i64, [L, i64]),
         "sttsm_workspace_bytes": (sz, [L, L, i32]),
         "sttsm": (ctypes.c_int, [L, vp, vp, i64, i64, L, vp, i32, vp, sz, vp]),
         "sttsm_all_but_one": (ctypes.c_int, [L, vp, vp, i64, i64, L, vp, i32, vp, sz, vp]),
@@ -99,7 +102,7 @@ def load():
 
 def exported_symbols():
     return ["bcss_num_blocks", "bcss_num_elems", "bcss_pack", "bcss_unpack", "bcss_fill_hashed", "bcss_symmetrize",
-            "sttsm_flops",
+            "sttsm_flops", "sttsm_vectors", "sttsm_vectors_workspace_bytes", "sttsm_vectors_flops",
             "sttsm_workspace_bytes", "sttsm", "sttsm_all_but_one", "sttsm_all_but_one_elems", "sttsm_workspace_temp", "sttsm_plan_info", "sttsm_profile_enable",
             "sttsm_profile_read", "sttsm_profile_disable", "sttsm_request_footprint", "sttsm_server_create",
             "sttsm_submit", "sttsm_poll", "sttsm_wait", "sttsm_fetch", "sttsm_server_stats", "sttsm_server_destroy",
@@ -223,6 +226,33 @@ def bcss_unpack(bcss, m: int, n: int, b: int, out=None, stream=None):
         raise ValueError("output too small or of the wrong dtype")
     _check(load().bcss_unpack(ctypes.byref(layout(m, n, b, dt)), _ptr(bcss), _ptr(out), _stream(stream)))
     return out
+
+
+def sttsm_vectors_flops(m: int, n: int, b: int, V: int) -> int:
+    return load().sttsm_vectors_flops(ctypes.byref(layout(m, n, b)), int(V))
+
+
+def sttsm_vectors(A_bcss, x, m: int, n: int, b: int, y=None, s=None, ws=None, stream=None):
+    """y_v = A x_v^(m-1) and s_v = A x_v^m for the rows x_v of x (V x n, A's
+    dtype).  Returns (y (V x n fp32), s (V fp32), ws)."""
+    import torch
+    dt = _torch_dtype_code(A_bcss)
+    if x.dtype != A_bcss.dtype or x.dim() != 2 or x.shape[1] != n or x.stride(1) != 1:
+        raise ValueError("x must be a (V, n) row-major tensor of A's dtype")
+    V = x.shape[0]
+    LA = layout(m, n, b, dt)
+    if y is None:
+        y = torch.empty(V, n, dtype=torch.float32, device=A_bcss.device)
+    if s is None:
+        s = torch.empty(V, dtype=torch.float32, device=A_bcss.device)
+    wsb = load().sttsm_vectors_workspace_bytes(ctypes.byref(LA), V)
+    if wsb == 0:
+        raise SttsmError(-1, "bad vector-product arguments")
+    if ws is None or ws.numel() < wsb:
+        ws = torch.empty(wsb, dtype=torch.uint8, device=A_bcss.device)
+    _check(load().sttsm_vectors(ctypes.byref(LA), _ptr(A_bcss), x.data_ptr(), V, x.stride(0), y.data_ptr(),
+                                y.stride(0), s.data_ptr(), _ptr(ws), ws.numel(), _stream(stream)))
+    return y, s, ws
 
 
 def bcss_symmetrize(bcss, m: int, n: int, b: int, stream=None):

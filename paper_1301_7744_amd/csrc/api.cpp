@@ -166,6 +166,46 @@ int bcss_unpack(const bcss_layout *L, const void *bcss, void *dense, void *strea
     return STTSM_OK;
 }
 
+size_t sttsm_vectors_workspace_bytes(const bcss_layout *A, int64_t V)
+{
+    std::string why;
+    if (!layout_ok(A, &why) || A->m < 2 || V < 1) return 0;
+    const int nbar = (int)((A->n + A->b - 1) / A->b);
+    const VecPlan *P = vec_plan_get(A->m, nbar, A->b, false, &why);
+    if (!P) return 0;
+    return std::max<size_t>(256, (size_t)P->chunk_u.size() * (size_t)V * (size_t)A->b * sizeof(float));
+}
+
+int64_t sttsm_vectors_flops(const bcss_layout *A, int64_t V)
+{
+    std::string why;
+    if (!layout_ok(A, &why) || A->m < 2 || V < 1) return -1;
+    const int nbar = (int)((A->n + A->b - 1) / A->b);
+    const VecPlan *P = vec_plan_get(A->m, nbar, A->b, false, &why);
+    if (!P) return -1;
+    return 2 * P->terms * V;
+}
+
+int sttsm_vectors(const bcss_layout *A, const void *A_dev, const void *x_dev, int64_t V, int64_t rs_x, float *y_dev,
+                  int64_t rs_y, float *s_dev, void *ws, size_t ws_bytes, void *stream)
+{
+    std::string why;
+    if (!layout_ok(A, &why)) return fail(STTSM_EINVAL, why);
+    if (A->m < 2) return fail(STTSM_EINVAL, "vector products need m >= 2");
+    if (A->dtype != STTSM_F32 && A->dtype != STTSM_BF16) return fail(STTSM_EINVAL, "A must be F32 or BF16");
+    if (V < 1) return fail(STTSM_EINVAL, "need at least one vector");
+    if (!A_dev || !x_dev || !y_dev || !ws) return fail(STTSM_EINVAL, "null buffer");
+    if (rs_x < A->n || rs_y < A->n) return fail(STTSM_EINVAL, "row strides must be >= n");
+    const int nbar = (int)((A->n + A->b - 1) / A->b);
+    const VecPlan *P = vec_plan_get(A->m, nbar, A->b, true, &why);
+    if (!P) return fail(STTSM_ENOMEM, why);
+    if (ws_bytes < sttsm_vectors_workspace_bytes(A, V)) return fail(STTSM_EINVAL, "workspace too small");
+    if (launch_vectors(A->dtype, A_dev, x_dev, rs_x, V, A->m, A->n, A->b, P->d_entries, P->d_chunk_begin,
+                       P->d_u_chunk, (int)P->chunk_u.size(), (float *)ws, y_dev, rs_y, s_dev, as_stream(stream)))
+        return fail(STTSM_EHIP, std::string("vector launch failed: ") + hipGetErrorString(hipGetLastError()));
+    return STTSM_OK;
+}
+
 int bcss_symmetrize(const bcss_layout *L, void *bcss, void *stream)
 {
     std::string why;

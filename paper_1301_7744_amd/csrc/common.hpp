@@ -53,6 +53,17 @@ struct GroupedTask {
 constexpr int kGroupedMT = 64;
 constexpr int kGroupedNT = 64;
 
+// One term of the vector product y = A x^(m-1): stored block `r` with the
+// free index at stored position q (the first position holding block index
+// u = s[q]), counted `w` times (the number of block tuples with leading
+// index u whose sorted form is s).  s holds the block's sorted indices.
+struct VecEntry {
+    int32_t r;
+    int32_t q;
+    float w;
+    int32_t s[kMaxOrder];
+};
+
 // Launch-wide parameters of one stage (kernel argument, passed by value).
 struct StageArgs {
     const void *in;          // input tensor (A in BCSS, or T^(k+1))

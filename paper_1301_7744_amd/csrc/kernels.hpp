@@ -1,4 +1,4 @@
-// Launchers of the gfx950 kernels (defined in kernels.hip, stage_bf16.hip and symmetrize.hip).  Each returns 0,
+// Launchers of the gfx950 kernels (defined in kernels.hip, stage_bf16.hip, symmetrize.hip and vectors.hip).  Each returns 0,
 // or -1 when the launch could not be made.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -36,6 +36,11 @@ int launch_grouped_bf16(int m, int b, int k, const StageArgs *d_stages, const Gr
 // In-place symmetrisation of the blocks with repeated indices (symmetrize.hip).
 int launch_symmetrize(int dtype, void *bcss, int m, int b, int64_t nblocks, const int32_t *d_tuples,
                       const int32_t *d_stab_start, const uint8_t *d_stab_perm, hipStream_t s);
+// Batched vector products y_v = A x_v^(m-1), s_v = x_v . y_v (vectors.hip);
+// part holds nchunks * V * b floats.
+int launch_vectors(int dtype, const void *A, const void *x, int64_t rs_x, int64_t V, int m, int64_t n, int b,
+                   const VecEntry *d_entries, const int32_t *d_chunk_begin, const int32_t *d_u_chunk, int nchunks,
+                   float *part, float *y, int64_t rs_y, float *s, hipStream_t st);
 int launch_prep_xt(int esize, const void *X, int64_t rs, int64_t cs, int64_t p, int64_t n, int64_t Kt, int64_t Pt,
                    float *xt, hipStream_t s);
 

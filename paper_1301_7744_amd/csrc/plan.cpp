@@ -11,6 +11,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <tuple>
 
 namespace symt {
 
@@ -492,6 +493,13 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err)
 }
 
 template <class T>
+static bool upload(const std::vector<T> &v, T **dst, std::string *err);
+template <class T>
+static bool upload_vec(const std::vector<T> &v, T **dst, std::string *err)
+{
+    return upload(v, dst, err);
+}
+template <class T>
 static bool upload(const std::vector<T> &v, T **dst, std::string *err)
 {
     *dst = nullptr;
@@ -654,6 +662,84 @@ const StabTable *stab_get(int m, std::string *err)
     if (!upload(T->start, &T->d_start, err) || !upload(T->perm, &T->d_perm, err)) return nullptr;
     const StabTable *out = T.get();
     g_stab.emplace(std::make_pair(dev, m), std::move(T));
+    return out;
+}
+
+namespace {
+std::map<std::tuple<int, int, int, int, bool>, std::unique_ptr<VecPlan>> g_vec;   // (device, m, nbar, b, upload)
+}
+
+const VecPlan *vec_plan_get(int m, int nbar, int b, bool upload, std::string *err)
+{
+    int dev = 0;
+    if (upload && hipGetDevice(&dev) != hipSuccess) {
+        *err = "hipGetDevice failed";
+        return nullptr;
+    }
+    if (m < 2 || m > kMaxOrder || nbar < 1 || b < 1) {
+        *err = "bad shape";
+        return nullptr;
+    }
+    const int64_t nblocks = binom((int64_t)nbar + m - 1, m);
+    if (nblocks < 0 || nblocks > (int64_t)INT32_MAX / kMaxOrder) {
+        *err = "too many blocks";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    const auto key = std::make_tuple(upload ? dev : -1, m, nbar, b, upload);
+    auto it = g_vec.find(key);
+    if (it != g_vec.end()) return it->second.get();
+    std::unique_ptr<VecPlan> P(new VecPlan);
+    P->m = m;
+    P->nbar = nbar;
+    P->b = b;
+    int64_t bm = 1;
+    for (int j = 0; j < m; ++j) bm *= b;
+    const std::vector<int32_t> tuples = sorted_tuples(m, nbar);
+    // factorials for the multinomial weights
+    double fact[kMaxOrder + 1];
+    fact[0] = 1;
+    for (int i = 1; i <= kMaxOrder; ++i) fact[i] = fact[i - 1] * i;
+    std::vector<std::vector<VecEntry>> per_u(nbar);
+    for (int64_t r = 0; r < nblocks; ++r) {
+        const int32_t *s = &tuples[r * m];
+        for (int q = 0; q < m; ++q) {
+            if (q > 0 && s[q] == s[q - 1]) continue;   // first position of each distinct index
+            // (m-1)! / prod over values of (count after removing one s[q])!
+            double w = fact[m - 1];
+            int i = 0;
+            while (i < m) {
+                int j = i;
+                while (j < m && s[j] == s[i]) ++j;
+                const int cnt = (j - i) - (s[i] == s[q] ? 1 : 0);
+                w /= fact[cnt];
+                i = j;
+            }
+            VecEntry e{};
+            e.r = (int32_t)r;
+            e.q = q;
+            e.w = (float)w;
+            for (int k = 0; k < m; ++k) e.s[k] = s[k];
+            per_u[s[q]].push_back(e);
+            P->terms += bm;
+        }
+    }
+    P->u_chunk.push_back(0);
+    for (int u = 0; u < nbar; ++u) {
+        const std::vector<VecEntry> &L = per_u[u];
+        for (size_t i = 0; i < L.size(); i += kVecChunk) {
+            P->chunk_begin.push_back((int32_t)P->entries.size() + (int32_t)i);
+            P->chunk_u.push_back(u);
+        }
+        P->entries.insert(P->entries.end(), L.begin(), L.end());
+        P->u_chunk.push_back((int32_t)P->chunk_u.size());
+    }
+    P->chunk_begin.push_back((int32_t)P->entries.size());
+    if (upload && (!upload_vec(P->entries, &P->d_entries, err) || !upload_vec(P->chunk_begin, &P->d_chunk_begin, err) ||
+                   !upload_vec(P->chunk_u, &P->d_chunk_u, err) || !upload_vec(P->u_chunk, &P->d_u_chunk, err)))
+        return nullptr;
+    const VecPlan *out = P.get();
+    g_vec.emplace(key, std::move(P));
     return out;
 }
 

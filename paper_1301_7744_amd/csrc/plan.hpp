@@ -110,6 +110,25 @@ const MetaTable *meta_get(int m, int nbar, int b, std::string *err);
 // when s_j == s_{j+1}.  The permutations of the m positions that map every
 // run onto itself (the tuple's stabiliser) for mask x are
 // perm[start[x]*m .. start[x+1]*m), m positions each, identity first.
+// Work list of the batched vector product for an order-m BCSS with nbar
+// blocks per mode: for every output block row u (0..nbar-1) the terms
+// (stored block, free position, weight) that add to y's rows u*b..u*b+b-1,
+// cut into chunks of at most kVecChunk terms; chunks of one u are
+// consecutive, u_chunk[u]..u_chunk[u+1].
+constexpr int kVecChunk = 4;
+struct VecPlan {
+    int m = 0, nbar = 0, b = 0;
+    std::vector<VecEntry> entries;
+    std::vector<int32_t> chunk_begin;   // per chunk: first entry; plus a final end
+    std::vector<int32_t> chunk_u;       // per chunk: its output block row
+    std::vector<int32_t> u_chunk;       // nbar + 1
+    int64_t terms = 0;                  // sum over entries of b^m (multiply-adds per vector)
+    VecEntry *d_entries = nullptr;
+    int32_t *d_chunk_begin = nullptr, *d_chunk_u = nullptr, *d_u_chunk = nullptr;
+};
+// Built on the host (and uploaded when upload is true), cached per device.
+const VecPlan *vec_plan_get(int m, int nbar, int b, bool upload, std::string *err);
+
 struct StabTable {
     int m = 0;
     std::vector<int32_t> start;   // 2^(m-1) + 1

@@ -148,3 +148,14 @@ def test_all_but_one_host_checks():
     assert lib.sttsm_all_but_one_elems(ctypes.byref(L1A), ctypes.byref(L1C), st.PREC_FP32) == -1
     rc = lib.sttsm_all_but_one(ctypes.byref(L1A), 1, 1, 10, 1, ctypes.byref(L1C), 1, st.PREC_FP32, None, 0, None)
     assert rc == -1
+
+
+@pytest.mark.parametrize("m,n,b,V", [(2, 10, 3, 4), (3, 35, 16, 7), (4, 9, 2, 3), (3, 256, 16, 64)])
+def test_vector_work_count(m, n, b, V):
+    """sttsm_vectors' term count: per vector, b^m for every stored block and
+    every distinct block index it holds (enumerated here independently)."""
+    import itertools
+    nbar = -(-n // b)
+    distinct = sum(len(set(t)) for t in itertools.combinations_with_replacement(range(nbar), m))
+    assert st.sttsm_vectors_flops(m, n, b, V) == 2 * V * b ** m * distinct
+    assert st.sttsm_vectors_flops(1, n, b, V) == -1

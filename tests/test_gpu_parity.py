@@ -493,3 +493,30 @@ def test_symmetrize_after_sttsm():
     for q in itertools.permutations(range(m)):
         assert np.array_equal(np.transpose(D, q), D)
     assert err(got, ref_bcss(A.astype(np.float64), X.astype(np.float64), b), m, p, b) <= TOL_FP32
+
+
+# ------------------------------------------------------------------ vector case
+@pytest.mark.parametrize("m,n,b,V,dt", [(2, 33, 8, 4, "f32"), (3, 16, 4, 5, "f32"), (3, 35, 16, 7, "f32"),
+                                        (4, 9, 2, 3, "f32"), (5, 7, 3, 6, "f32"), (3, 256, 16, 64, "f32"),
+                                        (3, 40, 8, 9, "bf16")])
+def test_vectors_vs_oracle(m, n, b, V, dt):
+    """y_v = A x_v^(m-1), s_v = A x_v^m on the GPU against the oracle (FP64
+    mode products) on the same values; repeated calls give identical bits."""
+    import torch
+    tdt = torch.float32 if dt == "f32" else torch.bfloat16
+    A = synth.symmetric_uniform(m, n, (m, n, 95))
+    X = synth.rng((m, n, 96)).standard_normal((V, n)).astype(np.float32)
+    if dt == "bf16":
+        A, X = synth.round_to_bf16(A), synth.round_to_bf16(X)
+    Ab = st().bcss_pack(dev_dense(np.asarray(A, np.float32), tdt), m, n, b)
+    Xd = torch.from_numpy(X).to(tdt).cuda()
+    y, s, ws = st().sttsm_vectors(Ab, Xd, m, n, b)
+    y2, s2, _ = st().sttsm_vectors(Ab, Xd, m, n, b, ws=ws)
+    torch.cuda.synchronize()
+    Y, S = oracle.vectors(A.astype(np.float64), X.astype(np.float64))
+    ey = float(np.linalg.norm(y.double().cpu().numpy() - Y) / np.linalg.norm(Y))
+    es = float(np.linalg.norm(s.double().cpu().numpy() - S) / np.linalg.norm(S))
+    tol = TOL_FP32 if dt == "f32" else tol_bf16(m)
+    say("vectors", m, n, b, V, dt, "rel err y", ey, "s", es)
+    assert ey <= tol and es <= tol
+    assert torch.equal(y, y2) and torch.equal(s, s2)

@@ -213,3 +213,25 @@ def test_all_but_one_symmetry_and_last_mode(m, n, p):
     for perm in itertools.permutations(range(1, m)):
         assert rel(np.transpose(T, (0,) + perm), T) <= TOL
     assert rel(oracle.mode_product(T, 0, X), oracle.direct_sum(A, X)) <= 1e-12
+
+
+# ---------------------------------------------------------------- vector case
+def test_vectors_matrix_case():
+    """m = 2: y = A x and s = x^T A x (library matrix products)."""
+    A = sym(2, 7, 67)
+    X = synth.rng(68).standard_normal((4, 7))
+    Y, s = oracle.vectors(A, X)
+    assert rel(Y, X @ A) <= TOL
+    assert rel(s, np.einsum("vi,ij,vj->v", X, A, X)) <= TOL
+
+
+@pytest.mark.parametrize("m,n,r", [(3, 6, 2), (4, 5, 3), (5, 4, 1)])
+def test_vectors_rank_r(m, n, r):
+    """Rank-r A: y = sum lam (a.x)^(m-1) a, s = sum lam (a.x)^m; and s = x . y."""
+    lams, vecs = synth.rank_r_factors(n, r, (m, n, 69))
+    A = synth.rank_r_symmetric(m, lams, vecs)
+    X = synth.rng((m, 70)).standard_normal((3, n))
+    Y, s = oracle.vectors(A, X)
+    Yc, sc = closed_forms.rank_r_vectors(lams, vecs, X, m)
+    assert rel(Y, Yc) <= 1e-12 and rel(s, sc) <= 1e-12
+    assert rel(s, np.sum(X * Y, axis=1)) <= 1e-12
