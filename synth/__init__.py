@@ -144,15 +144,15 @@ CONFIGS = {
 
 
 def rect_cases():
-    """m=4, p=32, rank-8 A: n in {128, 130}, bA in {4, 8, 16}, bC in {4, 8}."""
+    """m=4, p=32, rank-8 A: n in {128, 130}, bA in {4, 8, 16}, bC in {4, 8}.
+    The cases of one n share A and X (seed 401 + n), so the block sizes are
+    compared on the same tensor."""
     out = []
-    case = 0
     for n in (128, 130):
         for bA in (4, 8, 16):
             for bC in (4, 8):
                 out.append(dict(name="m4_n%d_p32_bA%d_bC%d" % (n, bA, bC), m=4, n=n, p=32,
-                                bA=bA, bC=bC, rank=8, seed=401 + case))
-                case += 1
+                                bA=bA, bC=bC, rank=8, seed=401 + n))
     return out
 
 

@@ -254,21 +254,37 @@ def test_order_sweep_full(name, prec, sweep_refs):
     assert e <= bound
 
 
+_RECT = {}
+
+
+def _rect_inputs(case):
+    """A (fp32), X, the oracle's C on those values and the closed form, per
+    (n, seed): shared by the block-size and precision variants."""
+    key = (case["m"], case["n"], case["p"], case["rank"], case["seed"])
+    if key not in _RECT:
+        m, n, p = case["m"], case["n"], case["p"]
+        lams, vecs = synth.rank_r_factors(n, case["rank"], case["seed"])
+        A = synth.rank_r_symmetric(m, lams, vecs).astype(np.float32)
+        X = synth.change_of_basis(p, n, case["seed"] + 1000)
+        Cref = oracle.chain(A.astype(np.float64), X.astype(np.float64))
+        Cclosed = closed_forms.rank_r(lams, vecs, X.astype(np.float64), m)
+
+        _RECT[key] = (A, X, Cref, Cclosed)
+    return _RECT[key]
+
+
 @pytest.mark.parametrize("prec", [P32, PBF])
 @pytest.mark.parametrize("case", synth.rect_cases(), ids=lambda c: c["name"])
 def test_rank8_rectangular(case, prec):
     """m=4, p=32, rank-8 A: against the closed form sum lam (X a)^{o4}."""
     m, n, p, bA, bC = case["m"], case["n"], case["p"], case["bA"], case["bC"]
     say("rect", case["name"], prec)
-    lams, vecs = synth.rank_r_factors(n, case["rank"], case["seed"])
-    A64 = synth.rank_r_symmetric(m, lams, vecs)
-    X = synth.change_of_basis(p, n, case["seed"] + 1000)
-    A = A64.astype(np.float32)
+    A, X, Cref, Cclosed = _rect_inputs(case)
     got = run(A, X, bA, bC, prec)
     # the GPU sees A rounded to fp32: compare with the exact result for those values
-    ref = bcss_ref.pack(oracle.chain(A.astype(np.float64), X.astype(np.float64)), bC)
+    ref = bcss_ref.pack(Cref, bC)
     e = err(got, ref, m, p, bC)
-    closed = bcss_ref.pack(closed_forms.rank_r(lams, vecs, X.astype(np.float64), m), bC)
+    closed = bcss_ref.pack(Cclosed, bC)
     e_closed = err(got, closed, m, p, bC)
     bound = TOL_FP32 if prec == P32 else tol_bf16(m)
     say("  rel err", e, "vs closed form", e_closed)
