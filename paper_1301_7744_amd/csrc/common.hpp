@@ -38,8 +38,10 @@ struct InEntry {
 
 struct Task {
     int32_t group;
-    int16_t mt;   // M tile index
-    int16_t nt;   // N tile index
+    int16_t mt;     // M tile index
+    int16_t nt;     // N tile index
+    int16_t noff;   // block-copy FP32 kernel: first column nt*NT + noff ...
+    int16_t ncol;   // ... and ncol valid columns (a tile may be split in two)
 };
 
 // Task of the grouped persistent kernel: a tile of one (request, level) stage.

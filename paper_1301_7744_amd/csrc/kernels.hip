@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -11,6 +12,8 @@ namespace symt {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16;
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
@@ -730,20 +733,27 @@ int launch_stage(const StageArgs &a, int compute, int MT, bool first, hipStream_
 // q (the same for the whole workgroup).  Rows of MT + 4 floats keep the
 // scatter and the MFMA operand reads free of bank conflicts.  X comes from a
 // transposed, zero-padded panel [k][n], so its loads need no bounds checks.
-// Global loads run two chunks ahead of the MFMAs.  The order M is a template
-// parameter so that every digit loop unrolls.
+// A chunk's global loads go out one chunk ahead of its MFMAs (registers, then
+// the second LDS buffer), and the block table entries they need one chunk
+// before that, so neither waits on LDS inside the MFMA loop.  Every thread
+// holds its LDS scatter address for each insertion position q < M, and picks
+// one with a wave-uniform select: staging reads no kernel argument and no
+// table in the loop.  The order M is a template parameter so that every digit
+// loop unrolls.
 constexpr int kFastMaxBlocks = 512;   // input blocks per group the LDS table holds
 
 template <int M, int MT, int NT, int KT, int PD, bool B_IS_IN, bool FIRST>
 __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
 {
     constexpr int RS = MT + 4, XS = NT + 4;
-    constexpr int WM = MT / 64, WN = 4 / WM;          // waves along M and N
-    constexpr int WTN = NT / WN, TM = 2, TN = WTN / 32;
+    // The four waves split the tile along M and each covers every column,
+    // so a tile with fewer valid columns shortens all four waves alike (each
+    // wave runs on its own SIMD: no SIMD idles while another has work).
+    constexpr int WTM = MT / 4, TM = WTM / 32, TN = NT / 32;
     constexpr int NF = MT * KT / 1024;                 // float4 of In per thread per chunk
     constexpr int XV = NT * KT / 4;                    // float4 of X per chunk
     constexpr int XF = (XV + 255) / 256;               // ... per thread
-    static_assert(WM * WN == 4 && TN >= 1 && NF >= 1, "tile");
+    static_assert(TM >= 1 && TN >= 1 && NF >= 1, "tile");
     __shared__ __attribute__((aligned(16))) float s_in[2][KT * RS];
     __shared__ __attribute__((aligned(16))) float s_x[2][KT * XS];
     __shared__ int32_t s_opart[MT];
@@ -753,24 +763,17 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave % WM, wn = wave / WM;
+    const int wm = wave;
     const Task task = a.tasks[blockIdx.x];
     const GroupDesc g = a.groups[task.group];
-    const int n0 = task.nt * NT;
-    const int Nvalid = g.jcount * a.bC;
+    const int n0 = task.nt * NT + task.noff;
+    const int ncol = task.ncol;   // valid columns from n0 (<= NT)
     const int k = a.k, bA = a.bA, nbar = a.nbar, G = a.chunk_blocks;
     const int sub4 = MT * bA / 4;                      // float4 per block part (>= 256)
     const float *in = (const float *)a.in;
     const float *xt = (const float *)a.xp;
     const int64_t xs = a.xt_stride;
 
-    // Per-launch tables from the host: stored digits of this thread's
-    // float4 (dig), and the output offset of each tile row (for M tile mt).
-    int dig[NF][M];
-#pragma unroll
-    for (int f = 0; f < NF; ++f)
-#pragma unroll
-        for (int i = 0; i < M; ++i) dig[f][i] = a.fdig[((task.mt * NF + f) * M + i) * 256 + tid];
     for (int i = tid; i < nbar; i += 256) {
         const InEntry ie = a.in_tab[g.in_row + i];
         s_ioff[i] = ie.off;
@@ -779,7 +782,7 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
     for (int mm = tid; mm < MT; mm += 256) s_opart[mm] = a.fopart[task.mt * MT + mm];
     for (int nn = tid; nn < NT; nn += 256) {
         const int ng = n0 + nn;
-        if (ng < Nvalid) {
+        if (nn < ncol) {
             const int jb = ng / a.bC, jj = ng - jb * a.bC;
             s_npart[nn] = g.out_base + (int64_t)jb * g.out_jstride + (int64_t)jj * a.osk;
         } else {
@@ -795,55 +798,95 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
         gq[f] = (256 * f) / sub4;
         o4[f] = task.mt * MT * bA + 4 * (F - gq[f] * sub4);
     }
+    // LDS address of this thread's float4 for every insertion position q
+    // (rows of this M tile start at 0), from its stored digits (host table,
+    // per M tile).  A register vector: the wave-uniform q indexes it without
+    // going through memory.
+    static_assert(M <= 8, "order");
+    using AdVec = typename std::conditional<M <= 4, i32x4, i32x8>::type;
+    AdVec adq[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        adq[f] = AdVec{};
+        int dg[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) dg[i] = a.fdig[((task.mt * NF + f) * M + i) * 256 + tid];
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            int ad = gq[f] * bA * RS - task.mt * MT;
+#pragma unroll
+            for (int i = 0; i < M; ++i) ad += dg[i] * a.lds[q][i];
+            adq[f][q] = ad;
+        }
+    }
     __syncthreads();
 
-    f32x4 rin[NF], rx[XF];
-    int rq[NF];
-    auto load_chunk = [&](int c) {
+    // Table entries (block offset, q) of the chunk to be loaded next; a
+    // block beyond nbar (last chunk only) reads block nbar-1 and gets q = -1.
+    int64_t toff[NF];
+    int tq[NF];
+    auto read_tab = [&](int c) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const int ib = c * G + gq[f];
-            if (ib < nbar) {
-                rq[f] = s_iq[ib];
-                rin[f] = *(const f32x4 *)(in + s_ioff[ib] + o4[f]);
-            } else {
-                rq[f] = -1;
-            }
+            const int ibc = ib < nbar ? ib : nbar - 1;
+            toff[f] = s_ioff[ibc];
+            tq[f] = ib < nbar ? s_iq[ibc] : -1;
+        }
+    };
+    // PD register sets of loaded chunks: chunk c is loaded into set c % PD,
+    // PD chunks before its MFMAs.  With PD = 2 the loads past the last chunk
+    // re-read it (never stored) so that every load is unconditional and the
+    // wait before a store covers only the older set.
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, PD - 1>;
+    f32x4 rin[PD][NF], rx[PD][XF];
+    int rq[PD][NF];
+    const int nch = a.nchunks;
+    auto load_chunk = [&](auto S, int c) {
+        constexpr int st = decltype(S)::value;
+        const int cx = c < nch ? c : nch - 1;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            rq[st][f] = tq[f];
+            rin[st][f] = *(const f32x4 *)(in + toff[f] + o4[f]);
         }
 #pragma unroll
         for (int f = 0; f < XF; ++f) {
             const int v = tid + 256 * f;
             const int xk = v / (NT / 4), xn = (v % (NT / 4)) * 4;
-            if (v < XV) rx[f] = *(const f32x4 *)(xt + (int64_t)(c * KT + xk) * xs + n0 + xn);
+            const int xc = xn < ncol ? xn : 0;   // columns past the tile are never used: stay in bounds
+            if (v < XV) rx[st][f] = *(const f32x4 *)(xt + (int64_t)(cx * KT + xk) * xs + n0 + xc);
         }
+        read_tab(c + 1);
     };
-    auto store_chunk = [&](int buf) {
+    auto store_chunk = [&](int buf, auto S) {
+        constexpr int st = decltype(S)::value;
         float *si = s_in[buf];
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            const int q = rq[f];
+            const int q = rq[st][f];
             // q is the same for the whole workgroup; q < 0 (block beyond
             // nbar, last chunk only) zero-fills in any layout
             const int qs = __builtin_amdgcn_readfirstlane(q < 0 ? k : q);
-            int ad = gq[f] * bA * RS - task.mt * MT;   // rows of this M tile start at 0
-#pragma unroll
-            for (int i = 0; i < M; ++i) ad += dig[f][i] * a.lds[qs][i];
-            const int s0 = a.lds[qs][0];
-            const f32x4 v = q < 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : rin[f];
-            if (s0 == 1) {
+            const int ad = adq[f][qs];
+            const f32x4 v = q < 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : rin[st][f];
+            // stored position 0 is the contracted mode (LDS stride RS) when
+            // q = 0, else mode 0 (stride 1: the float4 stays one LDS row)
+            if (qs != 0) {
                 *(f32x4 *)&si[ad] = v;
             } else {
                 si[ad] = v[0];
-                si[ad + s0] = v[1];
-                si[ad + 2 * s0] = v[2];
-                si[ad + 3 * s0] = v[3];
+                si[ad + RS] = v[1];
+                si[ad + 2 * RS] = v[2];
+                si[ad + 3 * RS] = v[3];
             }
         }
 #pragma unroll
         for (int f = 0; f < XF; ++f) {
             const int v = tid + 256 * f;
             const int xk = v / (NT / 4), xn = (v % (NT / 4)) * 4;
-            if (v < XV) *(f32x4 *)&s_x[buf][xk * XS + xn] = rx[f];
+            if (v < XV) *(f32x4 *)&s_x[buf][xk * XS + xn] = rx[st][f];
         }
     };
 
@@ -856,15 +899,13 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
     const int r32 = lane & 31, half = lane >> 5;
-    const int arow = wm * 64 + r32;          // this lane's M row in subtile 0
-    const int xcol = wn * WTN + r32;         // this lane's N column in subtile 0
-    const bool wave_live = n0 + wn * WTN < Nvalid;   // whole wave beyond N: skip its MFMAs
-    const int nch = a.nchunks;
+    const int arow = wm * WTM + r32;         // this lane's M row in subtile 0
+    const int xcol = r32;                    // this lane's N column in subtile 0
 
     // MFMAs of one chunk with the operands of the next k pair read from LDS
-    // before the current MFMAs issue; the next chunk's global loads go out
-    // after the first MFMA group, behind work already queued on the pipe.
-    auto mfma_chunk = [&](int buf, int c) {
+    // before the current MFMAs issue; the global loads of chunk c + PD go
+    // out after the first MFMA group, behind work already queued on the pipe.
+    auto mfma_chunk = [&](int buf, int c, auto S, auto O) {
         const float *si = s_in[buf];
         const float *sx = s_x[buf];
         float va[2][TM], vb[2][TN];
@@ -880,50 +921,81 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
             for (int i = 0; i < TM; ++i)
 #pragma unroll
                 for (int j = 0; j < TN; ++j) {
+                    if (j > 0 && 32 * j >= ncol) continue;   // 32-column subtile past the tile
                     if constexpr (B_IS_IN)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(vb[sl][j], va[sl][i], acc[i][j], 0, 0, 0);
                     else
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(va[sl][i], vb[sl][j], acc[i][j], 0, 0, 0);
                 }
         };
-        if (wave_live) rd(0, 0);
+        const bool live = c < nch;   // c = nch: the padding half of the last pair
+        if (live) rd(0, 0);
 #pragma unroll
         for (int t = 0; t < KT / 2; ++t) {
-            if (wave_live) {
+            if (live) {
                 if (t + 1 < KT / 2) rd(t + 1, (t + 1) & 1);
                 mf(t & 1);
             }
-            if (t == 0 && c + 1 < nch) load_chunk(c + 1);
+            if (t == 0) {
+                if constexpr (PD == 1) {
+                    if (c + 1 < nch) load_chunk(S, c + 1);
+                } else {
+                    load_chunk(S, c + 2);
+                }
+            }
+            // PD = 2: chunk c + 1 (set O, loaded a chunk ago) goes into the
+            // other LDS buffer while this wave's MFMAs drain; that buffer was
+            // last read before the barrier that opened this chunk.
+            if constexpr (PD == 2)
+                if (t == KT / 4) store_chunk(buf ^ 1, O);
         }
     };
 
-    load_chunk(0);
-    for (int c = 0; c < nch; ++c) {
-        store_chunk(c & 1);
+    read_tab(0);
+    if constexpr (PD == 1) {
+        load_chunk(I0{}, 0);
+        for (int c = 0; c < nch; ++c) {
+            store_chunk(c & 1, I0{});
+            __syncthreads();
+            mfma_chunk(c & 1, c, I0{}, I0{});
+        }
+    } else {
+        load_chunk(I0{}, 0);
+        load_chunk(I1{}, 1);
+        store_chunk(0, I0{});
         __syncthreads();
-        mfma_chunk(c & 1, c);
+        // Chunks go in pairs; with nch odd the second half of the last pair
+        // runs no MFMA, so that no load, store or barrier sits behind a
+        // branch (chunks past the last are staged and never read).
+        for (int c = 0; c < nch; c += 2) {
+            mfma_chunk(0, c, I0{}, I1{});
+            __syncthreads();
+            mfma_chunk(1, c + 1, I1{}, I0{});
+            __syncthreads();
+        }
     }
 
-    if (!wave_live) return;
     float *out = (float *)a.out;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
+        for (int j = 0; j < TN; ++j) {
+            if (j > 0 && 32 * j >= ncol) continue;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int rowi = 8 * (r >> 2) + 4 * half + (r & 3);
                 int mm, nn;
                 if constexpr (B_IS_IN) {
-                    mm = wm * 64 + i * 32 + r32;
-                    nn = wn * WTN + j * 32 + rowi;
+                    mm = wm * WTM + i * 32 + r32;
+                    nn = j * 32 + rowi;
                 } else {
-                    mm = wm * 64 + i * 32 + rowi;
-                    nn = wn * WTN + j * 32 + r32;
+                    mm = wm * WTM + i * 32 + rowi;
+                    nn = j * 32 + r32;
                 }
                 const int64_t np = s_npart[nn];
                 if (np >= 0) out[np + s_opart[mm]] = acc[i][j][r];
             }
+        }
 }
 
 template <int M, int MT, int NT, int KT, int PD>
@@ -941,7 +1013,7 @@ static void launch_fast_t(const StageArgs &a, bool first, hipStream_t s)
 
 // Tile shapes of the block-copy kernel (MT x NT, K chunk KT, prefetch depth PD).
 #define STTSM_FAST_TILES(X) X(256, 64, 16, 1) X(256, 128, 16, 1) X(256, 32, 16, 1) X(128, 64, 16, 1) \
-    X(128, 128, 16, 1) X(128, 64, 32, 1)
+    X(128, 128, 16, 1) X(128, 64, 32, 1) X(256, 64, 16, 2) X(128, 128, 16, 2) X(128, 64, 16, 2)
 
 template <int M>
 static int launch_fast_m(const StageArgs &a, int MT, int NT, int KT, int PD, bool first, hipStream_t s)

@@ -76,26 +76,98 @@ static TileCfg choose_tile(int Mblk)
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup i on XCD
-// i mod 8), each with its own L2.  Deal whole row groups to XCDs so that all
-// tiles of a group, which read the same input blocks, run on one XCD close
-// together in time: list position 8*l + x holds the l-th task of XCD x.
-static void order_tasks_for_xcds(std::vector<Task> *tasks)
+// i mod 8, each XCD with its own L2), and within an XCD round-robin over its
+// CUs: the l-th workgroup of an XCD shares a CU with the (l + cus)-th, where
+// cus = CUs per XCD (measured: the rotation's starting CU varies from launch
+// to launch, its period does not).  So the layout below
+//  - deals whole row groups to XCDs (all tiles of a group read the same
+//    input blocks), largest first to the XCD with the least work so far;
+//  - splits, when an XCD's last round is short (r tiles past a multiple of
+//    cus, 2r <= cus) and the kernel honours column ranges, r of its widest
+//    tiles into two column halves, so that no CU runs a whole tile more than
+//    the others;
+//  - spreads each XCD's tiles over its CU slots, largest first to the
+//    least-loaded slot (longest-processing-time order), within the number
+//    of tiles the dispatch order gives each slot; list position 8*l + x
+//    holds the l-th task of XCD x.
+// cost(t) is the work of tile t.
+template <class Cost>
+static void order_tasks_for_xcds(std::vector<Task> *tasks, Cost cost, int cus, bool split)
 {
     constexpr int kXcd = 8;
-    std::vector<std::vector<Task>> bins(kXcd);
-    size_t i = 0, gi = 0;
-    std::vector<size_t> load(kXcd, 0);
-    while (i < tasks->size()) {
+    struct Run {
+        size_t begin, end;
+        int64_t work, top;
+    };
+    std::vector<Run> runs;
+    for (size_t i = 0; i < tasks->size();) {
         size_t j = i;
-        while (j < tasks->size() && (*tasks)[j].group == (*tasks)[i].group) ++j;
-        // least-loaded XCD takes the next group (ties: round robin)
-        int best = (int)(gi % kXcd);
+        int64_t w = 0, top = 0;
+        while (j < tasks->size() && (*tasks)[j].group == (*tasks)[i].group) {
+            const int64_t c = cost((*tasks)[j]);
+            w += c;
+            top = std::max(top, c);
+            ++j;
+        }
+        runs.push_back(Run{i, j, w, top});
+        i = j;
+    }
+    std::stable_sort(runs.begin(), runs.end(), [](const Run &x, const Run &y) {
+        return x.top != y.top ? x.top > y.top : x.work > y.work;
+    });
+    std::vector<std::vector<Task>> bins(kXcd);
+    std::vector<int64_t> load(kXcd, 0);
+    for (size_t r = 0; r < runs.size(); ++r) {
+        int best = (int)(r % kXcd);   // ties: round robin
         for (int x = 0; x < kXcd; ++x)
             if (load[x] < load[best]) best = x;
-        for (size_t t = i; t < j; ++t) bins[best].push_back((*tasks)[t]);
-        load[best] += j - i;
-        ++gi;
-        i = j;
+        for (size_t t = runs[r].begin; t < runs[r].end; ++t) bins[best].push_back((*tasks)[t]);
+        load[best] += runs[r].work;
+    }
+    auto by_cost = [&](const Task &x, const Task &y) { return cost(x) > cost(y); };
+    const int S = std::max(cus, 1);
+    for (auto &b : bins) {
+        std::stable_sort(b.begin(), b.end(), by_cost);
+        const int r = (int)(b.size() % (size_t)S);
+        if (split && r > 0 && 2 * r <= S) {
+            std::vector<Task> halves;
+            int done = 0;
+            for (size_t t = 0; t < b.size() && done < r; ++t) {
+                Task &w = b[t];
+                if (w.ncol <= 32) continue;
+                const int h = (w.ncol / 32 + 1) / 2 * 32;   // first half: whole 32-column subtiles
+                Task second = w;
+                second.noff = (int16_t)(w.noff + h);
+                second.ncol = (int16_t)(w.ncol - h);
+                w.ncol = (int16_t)h;
+                halves.push_back(second);
+                ++done;
+            }
+            b.insert(b.end(), halves.begin(), halves.end());
+            std::stable_sort(b.begin(), b.end(), by_cost);
+        }
+        // The l-th task of this XCD runs on CU slot l mod S, so slot c runs
+        // cap(c) = ceil((n - c) / S) tasks.  Give each task, largest first,
+        // to the least-loaded slot with room left (longest processing time
+        // first under those counts), then lay the slots out in that order.
+        const size_t n = b.size();
+        if (n == 0) continue;
+        std::vector<int64_t> sl(S, 0);
+        std::vector<std::vector<int>> mine(S);
+        for (size_t t = 0; t < n; ++t) {
+            int best = -1;
+            for (int c = 0; c < S && (size_t)c < n; ++c) {
+                const size_t cap = (n - (size_t)c + S - 1) / S;
+                if (mine[c].size() >= cap) continue;
+                if (best < 0 || sl[c] < sl[best]) best = c;
+            }
+            mine[best].push_back((int)t);
+            sl[best] += cost(b[t]);
+        }
+        std::vector<Task> laid;
+        laid.reserve(n);
+        for (size_t l = 0; l < n; ++l) laid.push_back(b[mine[l % S][l / S]]);
+        b.swap(laid);
     }
     std::vector<Task> out;
     out.reserve(tasks->size());
@@ -148,7 +220,7 @@ static bool bf16_tile_override(int level, int *nt, int *kt, int *pd)
 
 static int kt_of(int compute) { return compute == CMP_FP32 ? 16 : 32; }
 
-bool plan_build_host(const PlanKey &key, Plan *P, std::string *err)
+bool plan_build_host(const PlanKey &key, Plan *P, std::string *err, int cus)
 {
     const int m = key.m;
     if (m < 1 || m > kMaxOrder || key.n < 1 || key.p < 1 || key.bA < 1 || key.bC < 1) {
@@ -406,18 +478,17 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err)
             // take half a block row (split along mode m-1, contiguous in
             // storage) when a half block still holds >= 256 float4.
             const bool can_half = k < m - 1 && bC % 2 == 0 && bA >= 8;
-            int64_t t64 = 0;
-            for (const GroupDesc &gd : S.groups) t64 += (gd.jcount * bC + 63) / 64;
             // Measured on m=3, n=p=256, b=16: a whole block row with 64
             // columns for the first level, half rows with 128 columns for
-            // middle levels and 64 for the last.
+            // middle levels, and half rows with 64 columns and loads two
+            // chunks ahead for the last.  The four waves always split the
+            // rows (WM = 4, WN = 1).
             S.tile = TileCfg{256, 64, 4, 1, 16, 1};
-            if (can_half) S.tile = k == 0 ? TileCfg{128, 64, 2, 2, 16, 1} : TileCfg{128, 128, 2, 2, 16, 1};
-            (void)t64;
+            if (can_half) S.tile = k == 0 ? TileCfg{128, 64, 4, 1, 16, 2} : TileCfg{128, 128, 4, 1, 16, 1};
             int tmt, tnt, tkt, tpd;
             if (fast_tile_override(d, &tmt, &tnt, &tkt, &tpd) && fast_tile_supported(tmt, tnt, tkt, tpd) &&
                 (tmt == 256 || can_half) && tkt % bA == 0)
-                S.tile = TileCfg{tmt, tnt, tmt / 64, 4 / (tmt / 64), tkt, tpd};
+                S.tile = TileCfg{tmt, tnt, 4, 1, tkt, tpd};
             a.chunk_blocks = S.tile.KT / bA;
             a.chunk_k = bA;
             a.chunks_per_blk = 1;
@@ -440,6 +511,13 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err)
                     else if (i <= k) j = i - 1;
                     else j = i;
                     a.lds[q][i] = j == k ? RS : (int32_t)ms[j];
+                }
+            // The kernel relies on stored position 0 having LDS stride RS for
+            // q = 0 and 1 otherwise.
+            for (int q = 0; q <= k; ++q)
+                if (a.lds[q][0] != (q == 0 ? RS : 1)) {
+                    *err = "block-copy staging: unexpected stride of stored position 0";
+                    return false;
                 }
             // Per-thread stored digits of the float4 each thread copies.
             const int MT = S.tile.MT, NF = MT * S.tile.KT / 1024, sub4 = MT * bA / 4;
@@ -472,10 +550,18 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err)
             const int N = S.groups[gi].jcount * bC;
             const int ntiles = (N + S.tile.NT - 1) / S.tile.NT;
             for (int mt = 0; mt < mtiles; ++mt)
-                for (int nt = 0; nt < ntiles; ++nt) S.tasks.push_back(Task{gi, (int16_t)mt, (int16_t)nt});
+                for (int nt = 0; nt < ntiles; ++nt)
+                    S.tasks.push_back(Task{gi, (int16_t)mt, (int16_t)nt, 0, (int16_t)std::min(S.tile.NT, N - nt * S.tile.NT)});
         }
-        order_tasks_for_xcds(&S.tasks);
-        if (mtiles > 32767 || S.tasks.size() > (size_t)INT32_MAX) {
+        {
+            // Work of a tile: MFMAs in whole 32-column subtiles, plus staging
+            // that does not shrink with the columns.
+            const int MT = S.tile.MT;
+            order_tasks_for_xcds(&S.tasks, [&](const Task &t) -> int64_t {
+                return (int64_t)std::min(MT, Mblk - t.mt * MT) * ((t.ncol + 31) / 32 * 32 + 16);
+            }, std::max(cus / 8, 1), S.fast);   // only the FP32 block-copy kernel reads noff / ncol
+        }
+        if (mtiles > 32767 || (int64_t)P->Ppad / S.tile.NT > 32767 || S.tasks.size() > (size_t)INT32_MAX) {
             *err = "too many tasks";
             return false;
         }
@@ -537,7 +623,9 @@ const Plan *plan_get(const PlanKey &key, std::string *err)
     auto it = g_plans.find(dk);
     if (it != g_plans.end()) return it->second.get();
     std::unique_ptr<Plan> P(new Plan);
-    if (!plan_build_host(key, P.get(), err)) return nullptr;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    if (!plan_build_host(key, P.get(), err, cus)) return nullptr;
     for (auto &S : P->stages) {
         if (!upload(S.groups, &S.d_groups, err) || !upload(S.in_tab, &S.d_in_tab, err) ||
             !upload(S.tasks, &S.d_tasks, err) || !upload(S.fdig, &S.d_fdig, err) ||

@@ -86,7 +86,9 @@ struct PlanKey {
 // Returns nullptr and fills *err on failure.
 const Plan *plan_get(const PlanKey &key, std::string *err);
 // Host part only (no device upload); for size queries.  Caller owns result.
-bool plan_build_host(const PlanKey &key, Plan *out, std::string *err);
+// cus: compute units of the device the plan runs on (the block-copy FP32
+// stages split tail tiles so that no CU gets more than one half tile extra).
+bool plan_build_host(const PlanKey &key, Plan *out, std::string *err, int cus = 256);
 
 // Meta-data tensor of App. B for an order-m BCSS with nbar blocks per mode:
 // for every block t (dimensional order over nbar^m) the rank of sort(t) and a
