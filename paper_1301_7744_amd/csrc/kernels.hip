@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <type_traits>
+#include <utility>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -733,14 +734,28 @@ int launch_stage(const StageArgs &a, int compute, int MT, bool first, hipStream_
 // q (the same for the whole workgroup).  Rows of MT + 4 floats keep the
 // scatter and the MFMA operand reads free of bank conflicts.  X comes from a
 // transposed, zero-padded panel [k][n], so its loads need no bounds checks.
-// A chunk's global loads go out one chunk ahead of its MFMAs (registers, then
-// the second LDS buffer), and the block table entries they need one chunk
-// before that, so neither waits on LDS inside the MFMA loop.  Every thread
+// A chunk's global loads go out PD chunks ahead of its MFMAs into one of PD
+// register sets; with PD = 1 a chunk is written to LDS between two MFMA
+// phases, with PD >= 2 in the middle of the previous chunk's MFMAs (the
+// other LDS buffer).  The block table entries a load needs are read one
+// chunk before it, so nothing waits on LDS inside the MFMA loop.  Every thread
 // holds its LDS scatter address for each insertion position q < M, and picks
 // one with a wave-uniform select: staging reads no kernel argument and no
 // table in the loop.  The order M is a template parameter so that every digit
 // loop unrolls.
 constexpr int kFastMaxBlocks = 512;   // input blocks per group the LDS table holds
+
+// f(integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time.
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, Is...>)
+{
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 template <int M, int MT, int NT, int KT, int PD, bool B_IS_IN, bool FIRST>
 __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
@@ -839,7 +854,6 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
     // re-read it (never stored) so that every load is unconditional and the
     // wait before a store covers only the older set.
     using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, PD - 1>;
     f32x4 rin[PD][NF], rx[PD][XF];
     int rq[PD][NF];
     const int nch = a.nchunks;
@@ -940,13 +954,13 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
                 if constexpr (PD == 1) {
                     if (c + 1 < nch) load_chunk(S, c + 1);
                 } else {
-                    load_chunk(S, c + 2);
+                    load_chunk(S, c + PD);
                 }
             }
-            // PD = 2: chunk c + 1 (set O, loaded a chunk ago) goes into the
-            // other LDS buffer while this wave's MFMAs drain; that buffer was
-            // last read before the barrier that opened this chunk.
-            if constexpr (PD == 2)
+            // PD >= 2: chunk c + 1 (set O, loaded PD - 1 chunks ago) goes
+            // into the other LDS buffer while this wave's MFMAs drain; that
+            // buffer was last read before the barrier that opened this chunk.
+            if constexpr (PD >= 2)
                 if (t == KT / 4) store_chunk(buf ^ 1, O);
         }
     };
@@ -960,18 +974,18 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
             mfma_chunk(c & 1, c, I0{}, I0{});
         }
     } else {
-        load_chunk(I0{}, 0);
-        load_chunk(I1{}, 1);
+        static_for<PD>([&](auto I) { load_chunk(I, (int)decltype(I)::value); });
         store_chunk(0, I0{});
         __syncthreads();
-        // Chunks go in pairs; with nch odd the second half of the last pair
-        // runs no MFMA, so that no load, store or barrier sits behind a
-        // branch (chunks past the last are staged and never read).
-        for (int c = 0; c < nch; c += 2) {
-            mfma_chunk(0, c, I0{}, I1{});
-            __syncthreads();
-            mfma_chunk(1, c + 1, I1{}, I0{});
-            __syncthreads();
+        // Chunks go in groups of PD; past the last chunk a group runs no
+        // MFMA, so that no load, store or barrier sits behind a branch
+        // (chunks past the last are staged and never read).
+        for (int c = 0; c < nch; c += PD) {
+            static_for<PD>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                mfma_chunk((c + i) & 1, c + i, I, std::integral_constant<int, (i + 1) % PD>{});
+                __syncthreads();
+            });
         }
     }
 
@@ -1013,7 +1027,8 @@ static void launch_fast_t(const StageArgs &a, bool first, hipStream_t s)
 
 // Tile shapes of the block-copy kernel (MT x NT, K chunk KT, prefetch depth PD).
 #define STTSM_FAST_TILES(X) X(256, 64, 16, 1) X(256, 128, 16, 1) X(256, 32, 16, 1) X(128, 64, 16, 1) \
-    X(128, 128, 16, 1) X(128, 64, 32, 1) X(256, 64, 16, 2) X(128, 128, 16, 2) X(128, 64, 16, 2)
+    X(128, 128, 16, 1) X(128, 64, 32, 1) X(256, 64, 16, 2) X(128, 128, 16, 2) X(128, 64, 16, 2) X(128, 128, 16, 3) \
+    X(128, 64, 16, 3) X(128, 64, 16, 4) X(128, 32, 16, 1) X(128, 32, 16, 2)
 
 template <int M>
 static int launch_fast_m(const StageArgs &a, int MT, int NT, int KT, int PD, bool first, hipStream_t s)

@@ -480,11 +480,11 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err, int cus)
             const bool can_half = k < m - 1 && bC % 2 == 0 && bA >= 8;
             // Measured on m=3, n=p=256, b=16: a whole block row with 64
             // columns for the first level, half rows with 128 columns for
-            // middle levels, and half rows with 64 columns and loads two
+            // middle levels, and half rows with 32 columns and loads two
             // chunks ahead for the last.  The four waves always split the
             // rows (WM = 4, WN = 1).
             S.tile = TileCfg{256, 64, 4, 1, 16, 1};
-            if (can_half) S.tile = k == 0 ? TileCfg{128, 64, 4, 1, 16, 2} : TileCfg{128, 128, 4, 1, 16, 1};
+            if (can_half) S.tile = k == 0 ? TileCfg{128, 32, 4, 1, 16, 2} : TileCfg{128, 128, 4, 1, 16, 1};
             int tmt, tnt, tkt, tpd;
             if (fast_tile_override(d, &tmt, &tnt, &tkt, &tpd) && fast_tile_supported(tmt, tnt, tkt, tpd) &&
                 (tmt == 256 || can_half) && tkt % bA == 0)
