@@ -761,6 +761,13 @@ template <int M, int MT, int NT, int KT, int PD, bool B_IS_IN, bool FIRST>
 __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
 {
     constexpr int RS = MT + 4, XS = NT + 4;
+    // Last level (mode 0 contracted, B_IS_IN false): the contracted mode is
+    // stored fastest in every block, so chunks are staged [row][k] (row
+    // stride RSK) with 16-byte writes, and each lane reads its 8 k values
+    // of a chunk with two 16-byte reads; the k pair t of the MFMA takes
+    // k = t (lanes 0-31) and t + 8 (lanes 32-63), X the same.
+    constexpr bool KMK = !B_IS_IN;
+    constexpr int RSK = KT + 4;
     // The four waves split the tile along M and each covers every column,
     // so a tile with fewer valid columns shortens all four waves alike (each
     // wave runs on its own SIMD: no SIMD idles while another has work).
@@ -769,7 +776,7 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
     constexpr int XV = NT * KT / 4;                    // float4 of X per chunk
     constexpr int XF = (XV + 255) / 256;               // ... per thread
     static_assert(TM >= 1 && TN >= 1 && NF >= 1, "tile");
-    __shared__ __attribute__((aligned(16))) float s_in[2][KT * RS];
+    __shared__ __attribute__((aligned(16))) float s_in[2][KMK ? MT * RSK : KT * RS];
     __shared__ __attribute__((aligned(16))) float s_x[2][KT * XS];
     __shared__ int32_t s_opart[MT];
     __shared__ int64_t s_npart[NT];
@@ -826,12 +833,19 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
         int dg[M];
 #pragma unroll
         for (int i = 0; i < M; ++i) dg[i] = a.fdig[((task.mt * NF + f) * M + i) * 256 + tid];
+        if constexpr (KMK) {
+            int row = -task.mt * MT;   // stored positions 1.. hold the row modes (q = 0)
 #pragma unroll
-        for (int q = 0; q < M; ++q) {
-            int ad = gq[f] * bA * RS - task.mt * MT;
+            for (int i = 1; i < M; ++i) row += dg[i] * a.lds[0][i];
+            adq[f][0] = row * RSK + gq[f] * bA + dg[0];
+        } else {
 #pragma unroll
-            for (int i = 0; i < M; ++i) ad += dg[i] * a.lds[q][i];
-            adq[f][q] = ad;
+            for (int q = 0; q < M; ++q) {
+                int ad = gq[f] * bA * RS - task.mt * MT;
+#pragma unroll
+                for (int i = 0; i < M; ++i) ad += dg[i] * a.lds[q][i];
+                adq[f][q] = ad;
+            }
         }
     }
     __syncthreads();
@@ -887,7 +901,7 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
             const f32x4 v = q < 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : rin[st][f];
             // stored position 0 is the contracted mode (LDS stride RS) when
             // q = 0, else mode 0 (stride 1: the float4 stays one LDS row)
-            if (qs != 0) {
+            if (KMK || qs != 0) {
                 *(f32x4 *)&si[ad] = v;
             } else {
                 si[ad] = v[0];
@@ -923,14 +937,17 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
         const float *si = s_in[buf];
         const float *sx = s_x[buf];
         float va[2][TM], vb[2][TN];
+        f32x4 vk[TM][KT / 8];   // KMK: this lane's k values t + 8 * half, t = 0 .. KT/2 - 1
         auto rd = [&](int t, int sl) {
-            const int kk = 2 * t + half;
+            const int kk = KMK ? t + (KT / 2) * half : 2 * t + half;
+            if constexpr (!KMK) {
 #pragma unroll
-            for (int i = 0; i < TM; ++i) va[sl][i] = si[kk * RS + arow + 32 * i];
+                for (int i = 0; i < TM; ++i) va[sl][i] = si[kk * RS + arow + 32 * i];
+            }
 #pragma unroll
             for (int j = 0; j < TN; ++j) vb[sl][j] = sx[kk * XS + xcol + 32 * j];
         };
-        auto mf = [&](int sl) {
+        auto mf = [&](int sl, int t) {
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -938,17 +955,28 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
                     if (j > 0 && 32 * j >= ncol) continue;   // 32-column subtile past the tile
                     if constexpr (B_IS_IN)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(vb[sl][j], va[sl][i], acc[i][j], 0, 0, 0);
+                    else if constexpr (KMK)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(vk[i][t / 4][t % 4], vb[sl][j], acc[i][j], 0, 0, 0);
                     else
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(va[sl][i], vb[sl][j], acc[i][j], 0, 0, 0);
                 }
         };
         const bool live = c < nch;   // c = nch: the padding half of the last pair
-        if (live) rd(0, 0);
+        if (live) {
+            if constexpr (KMK) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int h = 0; h < KT / 8; ++h)
+                        vk[i][h] = *(const f32x4 *)&si[(arow + 32 * i) * RSK + (KT / 2) * half + 4 * h];
+            }
+            rd(0, 0);
+        }
 #pragma unroll
         for (int t = 0; t < KT / 2; ++t) {
             if (live) {
                 if (t + 1 < KT / 2) rd(t + 1, (t + 1) & 1);
-                mf(t & 1);
+                mf(t & 1, t);
             }
             if (t == 0) {
                 if constexpr (PD == 1) {
