@@ -114,6 +114,9 @@ struct StageArgs {
     // block row, fopart[row].
     const int32_t *fdig;
     const int32_t *fopart;
+    // Block-copy FP32 kernel: one zero input block, read in place of the
+    // blocks past nbar that a last, partial K chunk covers.
+    const float *zero_blk;
 };
 
 

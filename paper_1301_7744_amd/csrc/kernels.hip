@@ -776,6 +776,7 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
     constexpr int XV = NT * KT / 4;                    // float4 of X per chunk
     constexpr int XF = (XV + 255) / 256;               // ... per thread
     static_assert(TM >= 1 && TN >= 1 && NF >= 1, "tile");
+    static_assert(KMK || 2 * KT * RS >= 4 * 1024, "epilogue staging fits the input buffers");
     __shared__ __attribute__((aligned(16))) float s_in[2][KMK ? MT * RSK : KT * RS];
     __shared__ __attribute__((aligned(16))) float s_x[2][KT * XS];
     __shared__ int32_t s_opart[MT];
@@ -851,7 +852,9 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
     __syncthreads();
 
     // Table entries (block offset, q) of the chunk to be loaded next; a
-    // block beyond nbar (last chunk only) reads block nbar-1 and gets q = -1.
+    // block past nbar (a partial last chunk, or a chunk past the last) reads
+    // the zero block, staged like a block with q = k.
+    const int64_t zoff = a.zero_blk - in;
     int64_t toff[NF];
     int tq[NF];
     auto read_tab = [&](int c) {
@@ -859,8 +862,10 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
         for (int f = 0; f < NF; ++f) {
             const int ib = c * G + gq[f];
             const int ibc = ib < nbar ? ib : nbar - 1;
-            toff[f] = s_ioff[ibc];
-            tq[f] = ib < nbar ? s_iq[ibc] : -1;
+            const int64_t o = s_ioff[ibc];
+            const int q = s_iq[ibc];
+            toff[f] = ib < nbar ? o : zoff;
+            tq[f] = ib < nbar ? q : k;
         }
     };
     // PD register sets of loaded chunks: chunk c is loaded into set c % PD,
@@ -893,12 +898,9 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
         float *si = s_in[buf];
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            const int q = rq[st][f];
-            // q is the same for the whole workgroup; q < 0 (block beyond
-            // nbar, last chunk only) zero-fills in any layout
-            const int qs = __builtin_amdgcn_readfirstlane(q < 0 ? k : q);
+            const int qs = __builtin_amdgcn_readfirstlane(rq[st][f]);   // the same for the whole workgroup
             const int ad = adq[f][qs];
-            const f32x4 v = q < 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : rin[st][f];
+            const f32x4 v = rin[st][f];
             // stored position 0 is the contracted mode (LDS stride RS) when
             // q = 0, else mode 0 (stride 1: the float4 stays one LDS row)
             if (KMK || qs != 0) {
@@ -1018,26 +1020,46 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
     }
 
     float *out = (float *)a.out;
+    if constexpr (B_IS_IN) {
+        // Output rows (mm) run along mode 0 of the output block, stride 1 in
+        // groups of four (mode 0 is not contracted here and its extent is a
+        // multiple of 4).  Each wave turns a 32 x 32 subtile around in LDS
+        // ([nn][mm], its own 4 KB of the staging buffer) so that every lane
+        // stores four consecutive entries with one 16-byte write.
+        __syncthreads();   // every wave is past its last read of the staging buffers
+        float *so = &s_in[0][0] + wave * 1024;
+        const int rr = lane >> 3, c4 = 4 * (lane & 7);
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            if (j > 0 && 32 * j >= ncol) continue;
+            for (int j = 0; j < TN; ++j) {
+                if (j > 0 && 32 * j >= ncol) continue;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int rowi = 8 * (r >> 2) + 4 * half + (r & 3);
-                int mm, nn;
-                if constexpr (B_IS_IN) {
-                    mm = wm * WTM + i * 32 + r32;
-                    nn = j * 32 + rowi;
-                } else {
-                    mm = wm * WTM + i * 32 + rowi;
-                    nn = j * 32 + r32;
+                for (int r = 0; r < 16; ++r) so[(8 * (r >> 2) + 4 * half + (r & 3)) * 32 + r32] = acc[i][j][r];
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int p4 = 0; p4 < 4; ++p4) {
+                    const int nl = rr + 8 * p4;
+                    const f32x4 v = *(const f32x4 *)&so[nl * 32 + c4];
+                    const int64_t np = s_npart[j * 32 + nl];
+                    if (np >= 0) *(f32x4 *)&out[np + s_opart[wm * WTM + i * 32 + c4]] = v;
                 }
-                const int64_t np = s_npart[nn];
-                if (np >= 0) out[np + s_opart[mm]] = acc[i][j][r];
+                __builtin_amdgcn_wave_barrier();
             }
-        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                if (j > 0 && 32 * j >= ncol) continue;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int mm = wm * WTM + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                    const int64_t np = s_npart[j * 32 + r32];
+                    if (np >= 0) out[np + s_opart[mm]] = acc[i][j][r];
+                }
+            }
+    }
 }
 
 template <int M, int MT, int NT, int KT, int PD>

@@ -512,6 +512,13 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err, int cus)
                     else j = i;
                     a.lds[q][i] = j == k ? RS : (int32_t)ms[j];
                 }
+            // Above the last level the kernel's epilogue stores four output
+            // rows at once: mode 0 must be the first row digit, with output
+            // stride 1 and an extent that is a multiple of 4.
+            if (k != 0 && (a.mmode[0] != 0 || a.mos[0] != 1 || a.mrad[0] % 4 != 0)) {
+                *err = "block-copy epilogue: rows not in runs of four";
+                return false;
+            }
             // The kernel relies on stored position 0 having LDS stride RS for
             // q = 0 and 1 otherwise.
             for (int q = 0; q <= k; ++q)
@@ -533,6 +540,7 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err, int cus)
                             r /= ext_in[i];
                         }
                     }
+            S.zero.assign((size_t)in_blk, 0.f);
             // Output offset of every block row.
             S.fopart.assign(Mblk, 0);
             for (int row = 0; row < Mblk; ++row) {
@@ -629,8 +637,9 @@ const Plan *plan_get(const PlanKey &key, std::string *err)
     for (auto &S : P->stages) {
         if (!upload(S.groups, &S.d_groups, err) || !upload(S.in_tab, &S.d_in_tab, err) ||
             !upload(S.tasks, &S.d_tasks, err) || !upload(S.fdig, &S.d_fdig, err) ||
-            !upload(S.fopart, &S.d_fopart, err))
+            !upload(S.fopart, &S.d_fopart, err) || !upload(S.zero, &S.d_zero, err))
             return nullptr;   // tables of a failed plan are leaked, never used
+        S.args.zero_blk = S.d_zero;
         S.args.fdig = S.d_fdig;
         S.args.fopart = S.d_fopart;
         S.args.groups = S.d_groups;

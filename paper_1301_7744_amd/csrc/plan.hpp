@@ -43,6 +43,8 @@ struct StagePlan {
     InEntry *d_in_tab = nullptr;
     Task *d_tasks = nullptr;
     int32_t *d_fdig = nullptr, *d_fopart = nullptr;
+    std::vector<float> zero;   // block-copy FP32 kernel: one zero input block
+    float *d_zero = nullptr;
     // Where the operands live: -1 means the caller's A (input) or C (output),
     // otherwise a byte offset into the workspace.
     int64_t in_ws = -1, out_ws = -1;
