@@ -218,8 +218,8 @@ int bcss_symmetrize(const bcss_layout *L, void *bcss, void *stream)
     if (!T) return fail(STTSM_ENOMEM, why);
     const StabTable *S = stab_get(L->m, &why);
     if (!S) return fail(STTSM_ENOMEM, why);
-    if (launch_symmetrize(L->dtype, bcss, L->m, L->b, bcss_num_blocks(L->m, nbar), T->d_tuples, S->d_start, S->d_perm,
-                          as_stream(stream)))
+    if (launch_symmetrize(L->dtype, bcss, L->m, L->b, T->d_tuples, T->d_rep_blocks, (int64_t)T->rep_blocks.size(),
+                          S->d_start, S->d_perm, S->d_pinv, as_stream(stream)))
         return fail(STTSM_EHIP, std::string("symmetrize launch failed: ") + hipGetErrorString(hipGetLastError()));
     return STTSM_OK;
 }

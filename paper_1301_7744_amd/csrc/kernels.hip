@@ -35,12 +35,18 @@ __device__ __forceinline__ float bf2f(u16 h) { return __uint_as_float(((uint32_t
 // fastest mode of both layouts: a wave reads and writes contiguous 4-entry
 // runs, and only the digits of the run's row (modes 1..m-1) are divided out.
 
+// A run of four consecutive entries moves as one vector when both ends are
+// contiguous and aligned (vec: n and b multiples of 4, pointers aligned to
+// four entries; the stored side also needs stride 1 along the run).
+template <class E>
+using Vec4 = E __attribute__((ext_vector_type(4)));
+
 // Stored block r (colex) of BCSS <- its sorted block of the dense tensor;
 // entries beyond n are written as zero.
 template <class E>
 __global__ void bcss_pack_kernel(const E *__restrict__ dense, E *__restrict__ bcss, int m, int64_t n, int b,
                                  int64_t bm, int64_t nblocks, const int32_t *__restrict__ tuples, int rows,
-                                 int runs)
+                                 int runs, int vec)
 {
     for (int64_t r = blockIdx.x; r < nblocks; r += gridDim.x) {
         int64_t base = 0, npow = 1;
@@ -66,6 +72,12 @@ __global__ void bcss_pack_kernel(const E *__restrict__ dense, E *__restrict__ bc
                 off += (int64_t)lj * np;
                 np *= n;
             }
+            if (vec && e0 + 4 <= b && (!ok || e0 + 4 <= lim0)) {
+                Vec4<E> v = {E(0), E(0), E(0), E(0)};
+                if (ok) v = *(const Vec4<E> *)&dense[off + e0];
+                *(Vec4<E> *)&out[(int64_t)row * b + e0] = v;
+                continue;
+            }
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int le = e0 + e;
@@ -81,7 +93,7 @@ template <class E>
 __global__ void bcss_unpack_kernel(const E *__restrict__ bcss, E *__restrict__ dense, int m, int64_t n, int b,
                                    int nbar, int64_t bm, int64_t nbm, const int64_t *__restrict__ rank,
                                    const int32_t *__restrict__ perm, const int32_t *__restrict__ pstr, int rows,
-                                   int runs)
+                                   int runs, int vec)
 {
     for (int64_t tb = blockIdx.x; tb < nbm; tb += gridDim.x) {
         int32_t tbj[kMaxOrder], ps[kMaxOrder];
@@ -110,10 +122,81 @@ __global__ void bcss_unpack_kernel(const E *__restrict__ bcss, E *__restrict__ d
                 np *= n;
             }
             if (!ok) continue;
+            if (vec && ps[0] == 1 && e0 + 4 <= b && e0 + 4 <= lim0) {
+                *(Vec4<E> *)&dense[off + e0] = *(const Vec4<E> *)&src[so + e0];
+                continue;
+            }
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int le = e0 + e;
                 if (le < b && le < lim0) dense[off + le] = src[so + (int64_t)le * ps[0]];
+            }
+        }
+    }
+}
+
+// The same with the stored block staged in LDS (blocks of at most
+// kUnpackLdsBytes): the block is read once with coalesced 16-byte vectors,
+// the permuted reads hit LDS, and every run goes out as one vector when the
+// dense side allows it.
+constexpr int kUnpackLdsBytes = 32768;
+
+template <class E>
+__global__ void bcss_unpack_lds_kernel(const E *__restrict__ bcss, E *__restrict__ dense, int m, int64_t n, int b,
+                                       int nbar, int bm, int64_t nbm, const int64_t *__restrict__ rank,
+                                       const int32_t *__restrict__ perm, const int32_t *__restrict__ pstr, int rows,
+                                       int runs, int vec, int src16)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char unpack_smem[];
+    E *sb = (E *)unpack_smem;
+    const int bytes = bm * (int)sizeof(E);
+    const bool vec16 = src16 && bytes % 16 == 0;   // every stored block starts 16-byte aligned
+    for (int64_t tb = blockIdx.x; tb < nbm; tb += gridDim.x) {
+        int32_t tbj[kMaxOrder], ps[kMaxOrder];
+        int64_t base = 0, npow = 1, q = tb;
+        const int32_t *pp = pstr + (int64_t)perm[tb] * m;
+        for (int j = 0; j < m; ++j) {
+            tbj[j] = (int32_t)(q % nbar) * b;
+            q /= nbar;
+            base += (int64_t)tbj[j] * npow;
+            npow *= n;
+            ps[j] = pp[j];
+        }
+        const E *src = bcss + rank[tb] * (int64_t)bm;
+        const int64_t lim0 = n - tbj[0];
+        __syncthreads();   // the previous block's reads of the staging buffer are done
+        if (vec16) {
+            for (int v = threadIdx.x; v < bytes / 16; v += blockDim.x) ((uint4 *)unpack_smem)[v] = ((const uint4 *)src)[v];
+        } else {
+            for (int v = threadIdx.x; v < bm; v += blockDim.x) sb[v] = src[v];
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < rows * runs; t += blockDim.x) {
+            const int row = t / runs, e0 = (t - row * runs) * 4;
+            int rr = row;
+            int64_t off = base, np = n;
+            int so = 0;
+            bool ok = true;
+            for (int j = 1; j < m; ++j) {
+                const int lj = rr % b;
+                rr /= b;
+                ok = ok && (int64_t)tbj[j] + lj < n;
+                off += (int64_t)lj * np;
+                so += lj * ps[j];
+                np *= n;
+            }
+            if (!ok) continue;
+            if (vec && e0 + 4 <= b && e0 + 4 <= lim0) {
+                Vec4<E> v;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = sb[so + (e0 + e) * ps[0]];
+                *(Vec4<E> *)&dense[off + e0] = v;
+                continue;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int le = e0 + e;
+                if (le < b && le < lim0) dense[off + le] = sb[so + le * ps[0]];
             }
         }
     }
@@ -125,8 +208,10 @@ static int launch_pack_t(const void *dense, void *bcss, int m, int64_t n, int b,
 {
     const int rows = (int)(bm / b), runs = (b + 3) / 4;
     const int64_t grid = std::min<int64_t>(std::max<int64_t>(nblocks, 1), 1 << 16);
+    const uintptr_t al = 4 * sizeof(E);
+    const int vec = n % 4 == 0 && b % 4 == 0 && (uintptr_t)dense % al == 0 && (uintptr_t)bcss % al == 0;
     hipLaunchKernelGGL(bcss_pack_kernel<E>, dim3((unsigned)grid), dim3(256), 0, s, (const E *)dense, (E *)bcss, m,
-                       n, b, bm, nblocks, tuples, rows, runs);
+                       n, b, bm, nblocks, tuples, rows, runs, vec);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -136,8 +221,15 @@ static int launch_unpack_t(const void *bcss, void *dense, int m, int64_t n, int 
 {
     const int rows = (int)(bm / b), runs = (b + 3) / 4;
     const int64_t grid = std::min<int64_t>(std::max<int64_t>(nbm, 1), 1 << 16);
-    hipLaunchKernelGGL(bcss_unpack_kernel<E>, dim3((unsigned)grid), dim3(256), 0, s, (const E *)bcss, (E *)dense,
-                       m, n, b, nbar, bm, nbm, rank, perm, pstr, rows, runs);
+    const uintptr_t al = 4 * sizeof(E);
+    const int vec = n % 4 == 0 && b % 4 == 0 && (uintptr_t)dense % al == 0 && (uintptr_t)bcss % al == 0;
+    if (bm * (int64_t)sizeof(E) <= kUnpackLdsBytes)
+        hipLaunchKernelGGL(bcss_unpack_lds_kernel<E>, dim3((unsigned)grid), dim3(256), (size_t)(bm * sizeof(E)), s,
+                           (const E *)bcss, (E *)dense, m, n, b, nbar, (int)bm, nbm, rank, perm, pstr, rows, runs, vec,
+                           (int)((uintptr_t)bcss % 16 == 0));
+    else
+        hipLaunchKernelGGL(bcss_unpack_kernel<E>, dim3((unsigned)grid), dim3(256), 0, s, (const E *)bcss, (E *)dense,
+                           m, n, b, nbar, bm, nbm, rank, perm, pstr, rows, runs, vec);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

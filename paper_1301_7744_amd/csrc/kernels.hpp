@@ -34,8 +34,9 @@ int launch_stage_bf16(const StageArgs &a, int NT, int KT, int PD, hipStream_t s)
 int launch_grouped_bf16(int m, int b, int k, const StageArgs *d_stages, const GroupedTask *d_tasks, int ntasks,
                         int *d_head, int grid, hipStream_t s);
 // In-place symmetrisation of the blocks with repeated indices (symmetrize.hip).
-int launch_symmetrize(int dtype, void *bcss, int m, int b, int64_t nblocks, const int32_t *d_tuples,
-                      const int32_t *d_stab_start, const uint8_t *d_stab_perm, hipStream_t s);
+int launch_symmetrize(int dtype, void *bcss, int m, int b, const int32_t *d_tuples, const int32_t *d_blocks,
+                      int64_t nlist, const int32_t *d_stab_start, const uint8_t *d_stab_perm,
+                      const int32_t *d_stab_pinv, hipStream_t s);
 // Batched vector products y_v = A x_v^(m-1), s_v = x_v . y_v (vectors.hip);
 // part holds nchunks * V * b floats.
 int launch_vectors(int dtype, const void *A, const void *x, int64_t rs_x, int64_t V, int m, int64_t n, int b,

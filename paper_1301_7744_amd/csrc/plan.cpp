@@ -711,8 +711,16 @@ const MetaTable *meta_get(int m, int nbar, int b, std::string *err)
             for (int j = 0; j < m; ++j) T->perm_strides.push_back((int32_t)bpow[pos[j]]);
         T->perm[f] = ins.first->second;
     }
+    const int64_t nblk = (int64_t)T->tuples.size() / m;
+    for (int64_t r = 0; r < nblk; ++r)
+        for (int j = 0; j + 1 < m; ++j)
+            if (T->tuples[r * m + j] == T->tuples[r * m + j + 1]) {
+                T->rep_blocks.push_back((int32_t)r);
+                break;
+            }
     if (!upload(T->rank, &T->d_rank, err) || !upload(T->perm, &T->d_perm, err) ||
-        !upload(T->perm_strides, &T->d_perm_strides, err) || !upload(T->tuples, &T->d_tuples, err))
+        !upload(T->perm_strides, &T->d_perm_strides, err) || !upload(T->tuples, &T->d_tuples, err) ||
+        !upload(T->rep_blocks, &T->d_rep_blocks, err))
         return nullptr;
     const MetaTable *out = T.get();
     g_meta.emplace(key, std::move(T));
@@ -751,12 +759,19 @@ const StabTable *stab_get(int m, std::string *err)
         do {
             bool keep = true;
             for (int j = 0; j < m && keep; ++j) keep = run[pi[j]] == run[j];
-            if (keep)
-                for (int j = 0; j < m; ++j) T->perm.push_back((uint8_t)pi[j]);
+            if (keep) {
+                int32_t inv[kMaxOrder] = {};
+                for (int j = 0; j < m; ++j) {
+                    T->perm.push_back((uint8_t)pi[j]);
+                    inv[pi[j]] = j;
+                }
+                T->pinv.insert(T->pinv.end(), inv, inv + kMaxOrder);
+            }
         } while (std::next_permutation(pi.begin(), pi.end()));
     }
     T->start.push_back((int32_t)(T->perm.size() / m));
-    if (!upload(T->start, &T->d_start, err) || !upload(T->perm, &T->d_perm, err)) return nullptr;
+    if (!upload(T->start, &T->d_start, err) || !upload(T->perm, &T->d_perm, err) || !upload(T->pinv, &T->d_pinv, err))
+        return nullptr;
     const StabTable *out = T.get();
     g_stab.emplace(std::make_pair(dev, m), std::move(T));
     return out;

@@ -102,7 +102,9 @@ struct MetaTable {
     std::vector<int32_t> perm;       // nbar^m
     std::vector<int32_t> perm_strides;
     std::vector<int32_t> tuples;     // sorted block tuples in colex order, m each
+    std::vector<int32_t> rep_blocks; // colex ranks of the tuples with a repeated index
     int64_t *d_rank = nullptr;
+    int32_t *d_rep_blocks = nullptr;
     int32_t *d_perm = nullptr;
     int32_t *d_perm_strides = nullptr;
     int32_t *d_tuples = nullptr;
@@ -137,8 +139,12 @@ struct StabTable {
     int m = 0;
     std::vector<int32_t> start;   // 2^(m-1) + 1
     std::vector<uint8_t> perm;
+    // pinv[p * kMaxOrder + i]: the position permutation p puts mode i at
+    // (perm[p * m + pinv] == i); entries past m are 0.
+    std::vector<int32_t> pinv;
     int32_t *d_start = nullptr;
     uint8_t *d_perm = nullptr;
+    int32_t *d_pinv = nullptr;
 };
 const StabTable *stab_get(int m, std::string *err);
 
