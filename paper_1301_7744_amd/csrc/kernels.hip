@@ -330,20 +330,29 @@ int launch_fill_hashed(int esize, void *bcss, int m, int64_t n, int b, int64_t n
 // Xp[j][i] = X(j, i) for j < p, i < n, zero elsewhere; rows of Kx entries.
 // Slot 0 fp32, slot 1 bf16(x), slot 2 bf16(x - bf16(x)).
 // Transposed fp32 panel: Xt[i][j] = X(j, i), Kt rows of Pt entries.
+// xt[i][j] = X[j][i] (zero outside p x n): one 64 x 64 tile per workgroup,
+// turned around in LDS so that X is read along i and xt written along j,
+// both contiguous for a row-major X.
 template <class E>
 __global__ void prep_xt_kernel(const E *__restrict__ X, int64_t rs, int64_t cs, int64_t p, int64_t n,
                                int64_t Kt, int64_t Pt, float *__restrict__ xt)
 {
-    const int64_t total = Kt * Pt;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = e / Pt, j = e - i * Pt;
+    __shared__ float t[64][65];
+    const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
+    const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+    for (int r = r0; r < 64; r += 4) {
+        const int64_t j = j0 + r, i = i0 + c;
         float v = 0.f;
         if (j < p && i < n) {
             if constexpr (sizeof(E) == 4) v = __uint_as_float(X[j * rs + i * cs]);
             else v = bf2f(X[j * rs + i * cs]);
         }
-        xt[e] = v;
+        t[r][c] = v;
+    }
+    __syncthreads();
+    for (int r = r0; r < 64; r += 4) {
+        const int64_t i = i0 + r, j = j0 + c;
+        if (i < Kt && j < Pt) xt[i * Pt + j] = t[c][r];
     }
 }
 
@@ -371,14 +380,15 @@ __global__ void prep_x_kernel(const E *__restrict__ X, int64_t rs, int64_t cs, i
 int launch_prep_xt(int esize, const void *X, int64_t rs, int64_t cs, int64_t p, int64_t n, int64_t Kt, int64_t Pt,
                    float *xt, hipStream_t s)
 {
-    const int64_t total = Kt * Pt;
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 1 << 16));
+    const int64_t gi = (Kt + 63) / 64, gj = (Pt + 63) / 64;
+    if (gi < 1 || gj < 1 || gi > INT32_MAX || gj > 65535) return -1;
+    const dim3 grid((unsigned)gi, (unsigned)gj);
     if (esize == 4)
-        hipLaunchKernelGGL(prep_xt_kernel<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s, (const uint32_t *)X,
-                           rs, cs, p, n, Kt, Pt, xt);
+        hipLaunchKernelGGL(prep_xt_kernel<uint32_t>, grid, dim3(256), 0, s, (const uint32_t *)X, rs, cs, p, n, Kt, Pt,
+                           xt);
     else if (esize == 2)
-        hipLaunchKernelGGL(prep_xt_kernel<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, s, (const uint16_t *)X,
-                           rs, cs, p, n, Kt, Pt, xt);
+        hipLaunchKernelGGL(prep_xt_kernel<uint16_t>, grid, dim3(256), 0, s, (const uint16_t *)X, rs, cs, p, n, Kt, Pt,
+                           xt);
     else
         return -1;
     return hipGetLastError() == hipSuccess ? 0 : -1;

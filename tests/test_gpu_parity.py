@@ -353,6 +353,37 @@ def test_block_copy_and_generic_kernels(m, n, p, bA, bC, generic, monkeypatch):
     assert np.all(got[padding_mask(m, p, bC)] == 0.0)
 
 
+# Every instantiated tile of the FP32 block-copy kernel that a level can
+# take (STTSM_FAST_TILE, one entry per level, empty = default): prefetch
+# depths 1-4, K chunks of 16 and 32, 32- to 128-column tiles.  The plan cache
+# is keyed by shape, not by the tile choice, so each case has its own n, p.
+FAST_TILE_CASES = [
+    ("256x64x16x2,128x128x16x2,128x64x16x2", 3, 101, 71),
+    (",128x128x16x3,128x64x16x3", 3, 103, 75),
+    (",128x64x16x4,128x64x16x4", 3, 105, 81),
+    ("256x32x16x1,128x32x16x1,128x32x16x2", 3, 99, 83),
+    ("256x128x16x1,128x64x32x1,128x64x32x1", 3, 97, 87),
+    ("128x128x16x1,128x64x16x2,256x64x16x1", 3, 94, 90),
+    ("256x64x16x2,256x64x16x1,256x64x16x2", 5, 11, 9),
+]
+
+
+@pytest.mark.parametrize("tiles,m,n,p", FAST_TILE_CASES, ids=[c[0] or "default" for c in FAST_TILE_CASES])
+def test_block_copy_tile_variants(tiles, m, n, p, monkeypatch):
+    """Each block-copy tile variant against the oracle on a ragged shape."""
+    monkeypatch.delenv("STTSM_GENERIC_KERNELS", raising=False)
+    monkeypatch.setenv("STTSM_FAST_TILE", tiles)
+    b = 16 if m == 3 else 4
+    say("tile variant", tiles, m, n, p, b)
+    A = synth.symmetric_uniform(m, n, (m, n, p, 93))
+    X = synth.change_of_basis(p, n, (m, n, p, 94))
+    got = run(A, X, b, b, P32)
+    e = err(got, ref_bcss(A.astype(np.float64), X.astype(np.float64), b), m, p, b)
+    say("  rel err", e)
+    assert e <= TOL_FP32
+    assert np.all(got[padding_mask(m, p, b)] == 0.0)
+
+
 # ------------------------------------------------------------------ bf16 block-copy kernel
 # (m, n, p, b): ragged n and p, K chunks that run past nbar, m = 4 M tiles.
 BF16_FAST_SHAPES = [(3, 40, 24, 8), (3, 35, 35, 16), (3, 100, 70, 16), (3, 130, 60, 16), (4, 33, 20, 8),
