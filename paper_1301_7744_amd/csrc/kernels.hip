@@ -957,9 +957,24 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
     // block past nbar (a partial last chunk, or a chunk past the last) reads
     // the zero block, staged like a block with q = k.
     const int64_t zoff = a.zero_blk - in;
+    // All of a thread's float4 of a chunk lie in one block when a block part
+    // holds every float4 of the chunk (bA = KT): one table entry, one q.
+    const bool one_block = gq[NF - 1] == 0;
     int64_t toff[NF];
     int tq[NF];
     auto read_tab = [&](int c) {
+        if (one_block) {
+            const int ib = c * G;
+            const int ibc = ib < nbar ? ib : nbar - 1;
+            const int64_t o = s_ioff[ibc];
+            const int q = s_iq[ibc];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                toff[f] = ib < nbar ? o : zoff;
+                tq[f] = ib < nbar ? q : k;
+            }
+            return;
+        }
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const int ib = c * G + gq[f];
@@ -998,6 +1013,22 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
     auto store_chunk = [&](int buf, auto S) {
         constexpr int st = decltype(S)::value;
         float *si = s_in[buf];
+        if (one_block) {
+            const int qs = __builtin_amdgcn_readfirstlane(rq[st][0]);
+            if (KMK || qs != 0) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) *(f32x4 *)&si[adq[f][qs]] = rin[st][f];
+            } else {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const int ad = adq[f][0];
+                    si[ad] = rin[st][f][0];
+                    si[ad + RS] = rin[st][f][1];
+                    si[ad + 2 * RS] = rin[st][f][2];
+                    si[ad + 3 * RS] = rin[st][f][3];
+                }
+            }
+        } else {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const int qs = __builtin_amdgcn_readfirstlane(rq[st][f]);   // the same for the whole workgroup
@@ -1013,6 +1044,7 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
                 si[ad + 2 * RS] = v[2];
                 si[ad + 3 * RS] = v[3];
             }
+        }
         }
 #pragma unroll
         for (int f = 0; f < XF; ++f) {
