@@ -92,6 +92,43 @@ static TileCfg choose_tile(int Mblk)
 //    holds the l-th task of XCD x.
 // cost(t) is the work of tile t.
 template <class Cost>
+static void order_tasks_for_xcds(std::vector<Task> *tasks, Cost cost, int cus, bool split);
+
+// Group-order layout: whole row groups dealt to the XCD with the fewest
+// tiles, each XCD keeping its groups' tiles in order, so the tiles that
+// share a row group's input blocks run next to each other in time.  When a
+// level has more tiles than the chip holds at once this locality decides
+// how often inputs come back from L2 rather than HBM (the bf16 block-copy
+// kernel on m = 4 shapes ran three times slower with its tiles reordered by
+// size), so every level uses it except an FP32 block-copy level whose tiles
+// are all resident at once, which gets the balanced placement below.
+static void order_tasks_group_major(std::vector<Task> *tasks)
+{
+    constexpr int kXcd = 8;
+    std::vector<std::vector<Task>> bins(kXcd);
+    std::vector<size_t> load(kXcd, 0);
+    size_t gi = 0;
+    for (size_t i = 0; i < tasks->size(); ++gi) {
+        size_t j = i;
+        while (j < tasks->size() && (*tasks)[j].group == (*tasks)[i].group) ++j;
+        int best = (int)(gi % kXcd);   // ties: round robin
+        for (int x = 0; x < kXcd; ++x)
+            if (load[x] < load[best]) best = x;
+        for (size_t t = i; t < j; ++t) bins[best].push_back((*tasks)[t]);
+        load[best] += j - i;
+        i = j;
+    }
+    std::vector<Task> out;
+    out.reserve(tasks->size());
+    size_t longest = 0;
+    for (auto &b : bins) longest = std::max(longest, b.size());
+    for (size_t l = 0; l < longest; ++l)
+        for (int x = 0; x < kXcd; ++x)
+            if (l < bins[x].size()) out.push_back(bins[x][l]);
+    tasks->swap(out);
+}
+
+template <class Cost>
 static void order_tasks_for_xcds(std::vector<Task> *tasks, Cost cost, int cus, bool split)
 {
     constexpr int kXcd = 8;
@@ -561,13 +598,22 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err, int cus)
                 for (int nt = 0; nt < ntiles; ++nt)
                     S.tasks.push_back(Task{gi, (int16_t)mt, (int16_t)nt, 0, (int16_t)std::min(S.tile.NT, N - nt * S.tile.NT)});
         }
-        {
-            // Work of a tile: MFMAs in whole 32-column subtiles, plus staging
-            // that does not shrink with the columns.
+        // Workgroups of the FP32 block-copy kernel a CU holds at once (LDS
+        // and registers of the instantiated tiles: three for 256-row or
+        // 128-column tiles, four or more for the narrower ones).
+        const int per_cu = S.tile.MT == 256 || S.tile.NT >= 128 ? 3 : 4;
+        if (S.fast && S.tasks.size() <= (size_t)per_cu * cus) {
+            // Every tile of the level is resident at once, so the order only
+            // decides which CU runs which tile: balance the CUs.  Work of a tile: MFMAs in whole
+            // 32-column subtiles, plus staging that does not shrink with the
+            // columns.  Only the FP32 block-copy kernel reads noff / ncol
+            // (so only it may split).
             const int MT = S.tile.MT;
             order_tasks_for_xcds(&S.tasks, [&](const Task &t) -> int64_t {
                 return (int64_t)std::min(MT, Mblk - t.mt * MT) * ((t.ncol + 31) / 32 * 32 + 16);
-            }, std::max(cus / 8, 1), S.fast);   // only the FP32 block-copy kernel reads noff / ncol
+            }, std::max(cus / 8, 1), true);
+        } else {
+            order_tasks_group_major(&S.tasks);
         }
         if (mtiles > 32767 || (int64_t)P->Ppad / S.tile.NT > 32767 || S.tasks.size() > (size_t)INT32_MAX) {
             *err = "too many tasks";
