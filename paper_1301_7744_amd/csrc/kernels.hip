@@ -442,6 +442,10 @@ struct CmpTraits<CMP_X3> {
     typedef u16 L;
 };
 
+// Input blocks per row group whose table the generic tile keeps in LDS
+// (larger groups read it from global memory).
+constexpr int kGenericTabBlocks = 256;
+
 // LDS of the generic tile.
 template <int CMP, int MT, int NT>
 struct GenericSmem {
@@ -453,6 +457,9 @@ struct GenericSmem {
     int32_t s_mpart[kMaxOrder][MT];   // input offset of row mm, per insertion position
     int32_t s_opart[MT];              // output offset of row mm (-1: beyond Mblk)
     int64_t s_npart[NT];              // output offset of column nn (-1: beyond N)
+    int32_t s_sqk[kMaxOrder];         // stride of the contracted mode, per insertion position
+    int64_t s_ioff[kGenericTabBlocks];   // the row group's input table (nbar <= kGenericTabBlocks)
+    int32_t s_iq[kGenericTabBlocks];
 };
 
 // One MT x NT tile of one row group (see the comment above); used by the
@@ -514,6 +521,14 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
             s_npart[nn] = -1;
         }
     }
+    if (tid <= a.k) sm.s_sqk[tid] = a.sq[tid][a.k];
+    const bool tab_lds = a.nbar <= kGenericTabBlocks;
+    if (tab_lds)
+        for (int i = tid; i < a.nbar; i += 256) {
+            const InEntry ie = a.in_tab[g.in_row + i];
+            sm.s_ioff[i] = ie.off;
+            sm.s_iq[i] = ie.q;
+        }
 
     // Per-thread staging assignment (fixed across chunks).
     // In: vector v -> row mm = v % MT, k-vector kv = v / MT.
@@ -549,8 +564,17 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
                     if (kk < kvalid) {
                         const int gi = kk / a.chunk_k;
                         const int lk = lk0 + (kk - gi * a.chunk_k);
-                        const InEntry ie = row[blk0 + gi];
-                        const int64_t off = ie.off + s_mpart[ie.q][mm] + (int64_t)lk * a.sq[ie.q][a.k];
+                        int64_t ioff;
+                        int iq;
+                        if (tab_lds) {
+                            ioff = sm.s_ioff[blk0 + gi];
+                            iq = sm.s_iq[blk0 + gi];
+                        } else {
+                            const InEntry ie = row[blk0 + gi];
+                            ioff = ie.off;
+                            iq = ie.q;
+                        }
+                        const int64_t off = ioff + s_mpart[iq][mm] + (int64_t)lk * sm.s_sqk[iq];
                         in_f[t][e] = a.in_f32 ? in32[off] : bf2f(in16[off]);
                     }
                 }
