@@ -330,17 +330,18 @@ int launch_fill_hashed(int esize, void *bcss, int m, int64_t n, int b, int64_t n
 // Xp[j][i] = X(j, i) for j < p, i < n, zero elsewhere; rows of Kx entries.
 // Slot 0 fp32, slot 1 bf16(x), slot 2 bf16(x - bf16(x)).
 // Transposed fp32 panel: Xt[i][j] = X(j, i), Kt rows of Pt entries.
-// xt[i][j] = X[j][i] (zero outside p x n): one 64 x 64 tile per workgroup,
-// turned around in LDS so that X is read along i and xt written along j,
-// both contiguous for a row-major X.
+// xt[i][j] = X[j][i] (zero outside p x n): one 16 x 16 tile per workgroup
+// (one entry per thread, so even a 256 x 256 panel spreads over 256
+// workgroups), turned around in LDS so that X is read along i and xt written
+// along j, both contiguous for a row-major X.
 template <class E>
 __global__ void prep_xt_kernel(const E *__restrict__ X, int64_t rs, int64_t cs, int64_t p, int64_t n,
                                int64_t Kt, int64_t Pt, float *__restrict__ xt)
 {
-    __shared__ float t[64][65];
-    const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
-    const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;
-    for (int r = r0; r < 64; r += 4) {
+    __shared__ float t[16][17];
+    const int64_t i0 = (int64_t)blockIdx.x * 16, j0 = (int64_t)blockIdx.y * 16;
+    const int c = threadIdx.x & 15, r = threadIdx.x >> 4;
+    {
         const int64_t j = j0 + r, i = i0 + c;
         float v = 0.f;
         if (j < p && i < n) {
@@ -350,10 +351,8 @@ __global__ void prep_xt_kernel(const E *__restrict__ X, int64_t rs, int64_t cs, 
         t[r][c] = v;
     }
     __syncthreads();
-    for (int r = r0; r < 64; r += 4) {
-        const int64_t i = i0 + r, j = j0 + c;
-        if (i < Kt && j < Pt) xt[i * Pt + j] = t[c][r];
-    }
+    const int64_t i = i0 + r, j = j0 + c;
+    if (i < Kt && j < Pt) xt[i * Pt + j] = t[c][r];
 }
 
 template <class E>
@@ -380,7 +379,7 @@ __global__ void prep_x_kernel(const E *__restrict__ X, int64_t rs, int64_t cs, i
 int launch_prep_xt(int esize, const void *X, int64_t rs, int64_t cs, int64_t p, int64_t n, int64_t Kt, int64_t Pt,
                    float *xt, hipStream_t s)
 {
-    const int64_t gi = (Kt + 63) / 64, gj = (Pt + 63) / 64;
+    const int64_t gi = (Kt + 15) / 16, gj = (Pt + 15) / 16;
     if (gi < 1 || gj < 1 || gi > INT32_MAX || gj > 65535) return -1;
     const dim3 grid((unsigned)gi, (unsigned)gj);
     if (esize == 4)
