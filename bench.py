@@ -71,8 +71,12 @@ def parse():
     ap.add_argument("--workload", default="m3_n256_b16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
-    ap.add_argument("--op", default="sttsm", choices=["sttsm", "all_but_one", "vectors"],
-                    help="sttsm, the product in all modes but mode 0, or batched vector products")
+    ap.add_argument("--op", default="sttsm", choices=["sttsm", "all_but_one", "vectors", "rank_update"],
+                    help="sttsm, the product in all modes but mode 0, batched vector products, or the "
+                         "rank-update form of sttsm")
+    ap.add_argument("--rows", default="1,4,16,0",
+                    help="--op rank_update: block rows per pass to time (0: all rows in one pass); the first is "
+                         "the reported value")
     ap.add_argument("--vectors", type=int, default=64, help="batch size V of --op vectors")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="minimum oracle time for the CPU baseline")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -324,6 +328,105 @@ def vectors_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def rank_update_bench(args):
+    """The rank-update form (passes of block rows, each a rank update of C)
+    against the chain on the same inputs: the chain on the generic kernels
+    (the same kernels the form runs on) and on the default kernels, each
+    captured in a HIP graph and replayed K times."""
+    import numpy as np
+    import torch
+    import paper_1301_7744_amd as st
+    import synth
+    cfg = synth.CONFIGS[args.workload]
+    m, n, p, bA, bC = cfg["m"], cfg["n"], cfg["p"], cfg["bA"], cfg["bC"]
+    prec = st.PREC_NAMES[args.prec]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("bench: generating inputs", args.workload)
+    A_np, X_np = synth.make_config_inputs(args.workload)
+    tdt = torch.float32
+    if args.prec == "bf16":
+        A_np, X_np, tdt = synth.round_to_bf16(A_np), synth.round_to_bf16(X_np), torch.bfloat16
+    A = st.bcss_pack(torch.from_numpy(np.ascontiguousarray(A_np.ravel(order="F"))).to(tdt).to(dev), m, n, bA)
+    X = torch.from_numpy(np.ascontiguousarray(X_np)).to(tdt).to(dev)
+    nbar = -(-n // bA)
+    flops = st.sttsm_flops(m, n, p, bA, bC)
+    stream = torch.cuda.current_stream()
+
+    def graph_ms(call):
+        for _ in range(max(1, args.warmup)):
+            call()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            call()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            call()
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    rows_list = [int(r) if int(r) > 0 else nbar for r in args.rows.split(",")]
+    sweep = {}
+    C_main = None
+    for rows in rows_list:
+        C, ws = st.sttsm_rank_update(A, X, m, n, p, bA, bC, prec, rows)
+        ms = graph_ms(lambda: st.sttsm_rank_update(A, X, m, n, p, bA, bC, prec, rows, C=C, ws=ws))
+        sweep[str(rows)] = {"ms": round(ms, 5), "passes": -(-nbar // rows), "workspace_mb": round(ws.numel() / 1e6, 2)}
+        log("bench: rank update, %d rows per pass: %.4f ms" % (rows, ms))
+        if C_main is None:
+            C_main = C.clone()
+        del C, ws
+    os.environ["STTSM_GENERIC_KERNELS"] = "1"
+    try:
+        Cg, wsg = st.sttsm(A, X, m, n, p, bA, bC, prec)
+        ms_gen = graph_ms(lambda: st.sttsm(A, X, m, n, p, bA, bC, prec, C=Cg, ws=wsg))
+    finally:
+        del os.environ["STTSM_GENERIC_KERNELS"]
+    Cd, wsd = st.sttsm(A, X, m, n, p, bA, bC, prec)
+    ms_def = graph_ms(lambda: st.sttsm(A, X, m, n, p, bA, bC, prec, C=Cd, ws=wsd))
+    log("bench: chain %.4f ms (generic kernels), %.4f ms (default kernels)" % (ms_gen, ms_def))
+    ms = sweep[str(rows_list[0])]["ms"]
+    peak = PEAK_TFLOPS[args.prec]
+    achieved = flops / (ms * 1e-3) / 1e12
+    out = {"metric": "sttsm rank-update form GFLOP/s (symmetry-aware count, Table 2 of the paper)",
+           "value": round(flops / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16" if args.prec == "bf16" else "f32",
+           "data": "synthetic (seeded; symmetric A uniform[-1,1] mirrored from sorted-index entries, X N(0,1)/sqrt(n))",
+           "config": {"workload": args.workload + "_rows%d" % rows_list[0], "m": m, "n": n, "p": p, "bA": bA,
+                      "bC": bC, "prec": args.prec, "rows_per_pass": rows_list[0], "launch": "graph replay"},
+           "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                        "frac": round(achieved / peak, 4), "traffic": None,
+                        "kernel": "whole step (every pass's two generic-kernel launches)"},
+           "rows_sweep": sweep,
+           "chain": {"generic_kernels_ms": round(ms_gen, 5), "default_kernels_ms": round(ms_def, 5),
+                     "workspace_mb": round(wsd.numel() / 1e6, 2),
+                     "generic_workspace_mb": round(wsg.numel() / 1e6, 2)}}
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle import bcss_ref
+        t = time.perf_counter()
+        Cref = oracle.rank_update(A_np.astype(np.float64), X_np.astype(np.float64), bA, rows_list[0])
+        t_cpu = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": round(flops / t_cpu / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": "full workload, dense FP64 rank-update form, 1 run, %.1f s" % t_cpu}
+        nb = st.bcss_num_blocks(m, -(-p // bC))
+        got = C_main.double().cpu().numpy().reshape(nb, bC ** m)
+        out["rel_err_vs_fp64"] = float("%.3e" % bcss_ref.rel_frobenius_bcss(got, bcss_ref.pack(Cref, bC), m, p, bC))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -335,6 +438,8 @@ def main():
         return serve_bench(args)
     if args.op == "vectors":
         return vectors_bench(args)
+    if args.op == "rank_update":
+        return rank_update_bench(args)
 
     import numpy as np
     import torch

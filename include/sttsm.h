@@ -172,6 +172,34 @@ int sttsm_all_but_one(const bcss_layout *A, const void *A_dev, const void *X_dev
 int64_t sttsm_all_but_one_elems(const bcss_layout *A, const bcss_layout *C, int32_t prec);
 
 /*
+ * The rank-update form of sttsm (the second algorithmic variant of §8, which
+ * the paper states for m = 2: with A split by rows A_i and X by columns X_i,
+ * C = X A X^T = sum_i X_i (A_i X^T)).  For order m the product Y = A x_1 X
+ * ... x_{m-1} X (the "all modes but one" tensor, symmetric in modes
+ * 1..m-1) has block rows Y_i = A_i x_1 X ... x_{m-1} X, and
+ * C = sum over the A-block indices i of Y_i x_0 X_{:,i}: a rank-bA update of
+ * C per block row.  The block rows are taken `rows` at a time: a pass forms
+ * its rows of Y in a buffer that holds one pass, then adds their update to C.
+ * Levels above Y run as in sttsm.  Result: the same C as sttsm, with the
+ * last contraction's sum split into passes (the first pass stores, each
+ * later one adds, in increasing i; the result is the same on every call).
+ * With rows >= nbar it is one pass and equals sttsm's result bit for bit when
+ * sttsm runs the generic kernels (environment STTSM_GENERIC_KERNELS=1).
+ *
+ * Arguments as for sttsm, plus rows >= 1 (EINVAL otherwise); needs m >= 2
+ * (EINVAL otherwise).  Every level runs on the generic staging kernel.
+ * ws    : at least sttsm_rank_update_workspace_bytes(A, C, prec, rows)
+ *         bytes, 256-byte aligned: the X panels, the temporaries
+ *         T^(m-1) .. T^(2) and one pass of Y (in place of all of T^(1)).
+ * Asynchronous on `stream`; C is fully overwritten.
+ */
+int sttsm_rank_update(const bcss_layout *A, const void *A_dev, const void *X_dev, int64_t rs_x, int64_t cs_x,
+                      const bcss_layout *C, void *C_dev, int32_t prec, int32_t rows, void *ws, size_t ws_bytes,
+                      void *stream);
+/* Workspace bytes of sttsm_rank_update; 0 on bad arguments (m < 2, rows < 1). */
+size_t sttsm_rank_update_workspace_bytes(const bcss_layout *A, const bcss_layout *C, int32_t prec, int32_t rows);
+
+/*
  * Batched vector products, the case of §2.5 where the matrix of sttsm is a
  * single vector (as in the CP decomposition): for V vectors x_v,
  *   y_v = A x_v^(m-1),  y_v[i] = sum_{i_2..i_m} a_{i i_2..i_m} x_v[i_2]...x_v[i_m],

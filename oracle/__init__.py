@@ -14,6 +14,7 @@ order (App. A).  X is a (p, n) array, ``X[j, i] = chi_{j i}``.
 Components
   direct_sum  (O1)  literal sum of §2.5 over all n^m terms, every output entry
   chain       (O2)  successive dense mode products (§5.2, Figure 1 bottom right)
+  rank_update       the rank-update form of §8 (C as a sum of rank-b updates)
   entry       (O3)  one output entry by the literal sum
   closed_forms (O4) m=2 matrix identity, rank-1 / rank-r forms
   bcss_ref          independent BCSS enumerator, pack and unpack
@@ -168,6 +169,30 @@ def all_but_one(A: np.ndarray, X: np.ndarray) -> np.ndarray:
         T = mode_product(T, k, X)
     return T
 
+
+
+def rank_update(A: np.ndarray, X: np.ndarray, b: int, rows: int = 1) -> np.ndarray:
+    """The rank-update form of sttsm, the second algorithmic variant of §8.
+    The paper gives it for m = 2: with A split into rows A_i and X into
+    columns X_i, C = X A X^T = sum_i X_i (A_i X^T).  For order m the rows
+    of A x_1 X ... x_{m-1} X (all_but_one) take the place of A_i X^T, and
+    each adds its product with column block X_{:, i} in mode 0 to C.  Rows
+    go in blocks of b (the last one ragged), `rows` blocks per pass, passes
+    in increasing i.  FP64, Fortran order, extent p in every mode."""
+    A = _as_dense_f64(A)
+    X = np.asarray(X, dtype=np.float64)
+    m, n, p = _check(A, X)
+    if m < 2:
+        raise ValueError("needs order m >= 2")
+    if b < 1 or rows < 1:
+        raise ValueError("b and rows must be >= 1")
+    Y = all_but_one(A, X)
+    C = np.zeros((p,) * m, dtype=np.float64, order="F")
+    w = b * rows
+    for i0 in range(0, n, w):
+        i1 = min(i0 + w, n)
+        C += mode_product(Y[i0:i1], 0, X[:, i0:i1])
+    return C
 
 
 def vectors(A: np.ndarray, X: np.ndarray):

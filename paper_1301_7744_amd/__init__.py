@@ -71,6 +71,8 @@ def load():
         "sttsm": (ctypes.c_int, [L, vp, vp, i64, i64, L, vp, i32, vp, sz, vp]),
         "sttsm_all_but_one": (ctypes.c_int, [L, vp, vp, i64, i64, L, vp, i32, vp, sz, vp]),
         "sttsm_all_but_one_elems": (i64, [L, L, i32]),
+        "sttsm_rank_update": (ctypes.c_int, [L, vp, vp, i64, i64, L, vp, i32, i32, vp, sz, vp]),
+        "sttsm_rank_update_workspace_bytes": (sz, [L, L, i32, i32]),
         "sttsm_workspace_temp": (ctypes.c_int, [L, L, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(i32),
                                                 ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "sttsm_plan_info": (ctypes.c_int, [L, L, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i64),
@@ -103,7 +105,8 @@ def load():
 def exported_symbols():
     return ["bcss_num_blocks", "bcss_num_elems", "bcss_pack", "bcss_unpack", "bcss_fill_hashed", "bcss_symmetrize",
             "sttsm_flops", "sttsm_vectors", "sttsm_vectors_workspace_bytes", "sttsm_vectors_flops",
-            "sttsm_workspace_bytes", "sttsm", "sttsm_all_but_one", "sttsm_all_but_one_elems", "sttsm_workspace_temp", "sttsm_plan_info", "sttsm_profile_enable",
+            "sttsm_workspace_bytes", "sttsm", "sttsm_all_but_one", "sttsm_all_but_one_elems", "sttsm_rank_update",
+            "sttsm_rank_update_workspace_bytes", "sttsm_workspace_temp", "sttsm_plan_info", "sttsm_profile_enable",
             "sttsm_profile_read", "sttsm_profile_disable", "sttsm_request_footprint", "sttsm_server_create",
             "sttsm_submit", "sttsm_poll", "sttsm_wait", "sttsm_fetch", "sttsm_server_stats", "sttsm_server_destroy",
             "sttsm_last_error", "sttsm_version"]
@@ -162,7 +165,8 @@ def sttsm_workspace_bytes(m: int, n: int, p: int, bA: int, bC: int, prec: int = 
 
 
 @functools.lru_cache(maxsize=256)
-def _workspace_temp(m, n, p, bA, bC, prec, k, dtype):
+def _workspace_temp(m, n, p, bA, bC, prec, k, dtype, generic_env):
+    # generic_env: the STTSM_GENERIC_KERNELS setting, which changes the plan
     off, dt = ctypes.c_size_t(), ctypes.c_int32()
     nj, npf, blk = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     _check(load().sttsm_workspace_temp(ctypes.byref(layout(m, n, bA, dtype)), ctypes.byref(layout(m, p, bC)), prec,
@@ -173,7 +177,8 @@ def _workspace_temp(m, n, p, bA, bC, prec, k, dtype):
 
 def sttsm_workspace_temp(m: int, n: int, p: int, bA: int, bC: int, prec: int, k: int, dtype: int = F32) -> dict:
     """Where T^(k) sits in sttsm's workspace (cached per shape)."""
-    off, dt, nj, npf, blk = _workspace_temp(int(m), int(n), int(p), int(bA), int(bC), int(prec), int(k), int(dtype))
+    off, dt, nj, npf, blk = _workspace_temp(int(m), int(n), int(p), int(bA), int(bC), int(prec), int(k), int(dtype),
+                                            os.environ.get("STTSM_GENERIC_KERNELS", ""))
     return dict(byte_offset=off, dtype=dt, num_jtuples=nj, num_prefixes=npf, block_elems=blk)
 
 
@@ -321,6 +326,42 @@ def sttsm_all_but_one(A_bcss, X, m: int, n: int, p: int, bA: int, bC: int, prec:
     _check(load().sttsm_all_but_one(ctypes.byref(LA), _ptr(A_bcss), X.data_ptr(), X.stride(0), X.stride(1),
                                     ctypes.byref(LC), _ptr(T), prec, _ptr(ws), ws.numel(), _stream(stream)))
     return T[:ne].view(info["num_jtuples"], info["num_prefixes"], info["block_elems"]), ws
+
+
+def sttsm_rank_update_workspace_bytes(m: int, n: int, p: int, bA: int, bC: int, prec: int, rows: int,
+                                      dtype: int = F32) -> int:
+    LA, LC = layout(m, n, bA, dtype), layout(m, p, bC, F32)
+    wsb = load().sttsm_rank_update_workspace_bytes(ctypes.byref(LA), ctypes.byref(LC), prec, rows)
+    if wsb == 0:
+        raise SttsmError(-1, load().sttsm_last_error().decode())
+    return wsb
+
+
+def sttsm_rank_update(A_bcss, X, m: int, n: int, p: int, bA: int, bC: int, prec: int = PREC_FP32, rows: int = 1,
+                      C=None, ws=None, stream=None):
+    """C := [A; X, ..., X] by the rank-update form: passes of `rows` block
+    rows of A x_1 X ... x_{m-1} X, each added to C as a rank update.
+    Returns (C, ws)."""
+    import torch
+    dt = _torch_dtype_code(A_bcss)
+    if X.dtype != A_bcss.dtype or X.dim() != 2 or tuple(X.shape) != (p, n):
+        raise ValueError("X must be a (p, n) tensor of A's dtype")
+    LA, LC = layout(m, n, bA, dt), layout(m, p, bC, F32)
+    if A_bcss.numel() < bcss_num_elems(m, n, bA, dt):
+        raise ValueError("A too small for its layout")
+    nc = bcss_num_elems(m, p, bC, F32)
+    if C is None:
+        C = torch.empty(nc, dtype=torch.float32, device=A_bcss.device)
+    elif C.numel() < nc or C.dtype != torch.float32:
+        raise ValueError("C too small or not float32")
+    wsb = load().sttsm_rank_update_workspace_bytes(ctypes.byref(LA), ctypes.byref(LC), prec, rows)
+    if wsb == 0:
+        raise SttsmError(-1, load().sttsm_last_error().decode())
+    if ws is None or ws.numel() < wsb:
+        ws = torch.empty(wsb, dtype=torch.uint8, device=A_bcss.device)
+    _check(load().sttsm_rank_update(ctypes.byref(LA), _ptr(A_bcss), X.data_ptr(), X.stride(0), X.stride(1),
+                                    ctypes.byref(LC), _ptr(C), prec, rows, _ptr(ws), ws.numel(), _stream(stream)))
+    return C, ws
 
 
 def temporary(ws, m: int, n: int, p: int, bA: int, bC: int, prec: int, k: int, dtype: int = F32):

@@ -393,6 +393,87 @@ int sttsm_all_but_one(const bcss_layout *A, const void *A_dev, const void *X_dev
     return run_levels(A, A_dev, X_dev, rs_x, cs_x, C, prec, 1, T_dev, ws, ws_bytes, stream);
 }
 
+size_t sttsm_rank_update_workspace_bytes(const bcss_layout *A, const bcss_layout *C, int32_t prec, int32_t rows)
+{
+    PlanKey key;
+    if (make_key(A, C, prec, &key) != STTSM_OK) return 0;
+    if (A->m < 2) {
+        fail(STTSM_EINVAL, "the rank-update form needs m >= 2");
+        return 0;
+    }
+    key.generic_only = true;
+    Plan P;
+    RankPlan R;
+    std::string why;
+    if (!plan_build_host(key, &P, &why) || !rank_plan_build_host(P, rows, &R, &why)) {
+        fail(STTSM_EINVAL, why);
+        return 0;
+    }
+    return R.ws_bytes;
+}
+
+int sttsm_rank_update(const bcss_layout *A, const void *A_dev, const void *X_dev, int64_t rs_x, int64_t cs_x,
+                      const bcss_layout *C, void *C_dev, int32_t prec, int32_t rows, void *ws, size_t ws_bytes,
+                      void *stream)
+{
+    PlanKey key;
+    int rc = make_key(A, C, prec, &key);
+    if (rc != STTSM_OK) return rc;
+    if (A->m < 2) return fail(STTSM_EINVAL, "the rank-update form needs m >= 2");
+    if (rows < 1) return fail(STTSM_EINVAL, "rows per pass must be >= 1");
+    if (!A_dev || !X_dev || !C_dev) return fail(STTSM_EINVAL, "null buffer");
+    if (((uintptr_t)ws & 255) != 0) return fail(STTSM_EINVAL, "workspace must be 256-byte aligned");
+    std::string why;
+    const RankPlan *R = rank_plan_get(key, rows, &why);
+    if (!R) return fail(STTSM_ENOMEM, why);
+    if (ws_bytes < R->ws_bytes || !ws) return fail(STTSM_EINVAL, "workspace too small");
+    const Plan *P = R->chain;
+    hipStream_t s = as_stream(stream);
+    char *w = (char *)ws;
+    float *x32 = P->xp_off[0] >= 0 ? (float *)(w + P->xp_off[0]) : nullptr;
+    uint16_t *xhi = P->xp_off[1] >= 0 ? (uint16_t *)(w + P->xp_off[1]) : nullptr;
+    uint16_t *xlo = P->xp_off[2] >= 0 ? (uint16_t *)(w + P->xp_off[2]) : nullptr;
+    if ((x32 || xhi || xlo) &&
+        launch_prep_x(dtype_size(A->dtype), X_dev, rs_x, cs_x, P->p, P->n, P->Ppad, P->Kx, x32, xhi, xlo, s))
+        return fail(STTSM_EHIP, std::string("X panel launch failed: ") + hipGetErrorString(hipGetLastError()));
+    // X panel of a level, from column k0 on (fp32 panel: float, else bf16).
+    auto panel = [&](int slot, int64_t k0) -> const void * {
+        if (slot == 0) return x32 ? (const void *)(x32 + k0) : nullptr;
+        if (slot == 1) return xhi ? (const void *)(xhi + k0) : nullptr;
+        if (slot == 2) return xlo ? (const void *)(xlo + k0) : nullptr;
+        return nullptr;
+    };
+    auto run = [&](const StagePlan &S, const void *in, void *out, int64_t k0) -> int {
+        StageArgs a = S.args;
+        a.in = in;
+        a.out = out;
+        a.xp = panel(S.xp_slot, k0);
+        a.xp_lo = S.xp_lo_slot >= 0 ? panel(S.xp_lo_slot, k0) : nullptr;
+        if (!a.xp || (S.xp_lo_slot >= 0 && !a.xp_lo)) return fail(STTSM_EINVAL, "X panel missing from the plan");
+        const long slot = prof_slot(S.d);
+        if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot], s);
+        if (launch_stage(a, S.compute, S.tile.MT, S.d == 0, s))
+            return fail(STTSM_EHIP, std::string("stage launch failed: ") + hipGetErrorString(hipGetLastError()));
+        if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot + 1], s);
+        return STTSM_OK;
+    };
+    // Levels above the last temporary, as in the chain.
+    for (int d = 0; d + 2 < P->m; ++d) {
+        const StagePlan &S = P->stages[d];
+        rc = run(S, S.in_ws < 0 ? A_dev : (const void *)(w + S.in_ws), w + S.out_ws, 0);
+        if (rc != STTSM_OK) return rc;
+    }
+    // Passes: rows of T^(1) into the buffer, then their update of C.
+    void *buf = w + R->buf_off;
+    for (const RankPass &ps : R->passes) {
+        rc = run(ps.row, ps.row.in_ws < 0 ? A_dev : (const void *)(w + ps.row.in_ws), buf, 0);
+        if (rc != STTSM_OK) return rc;
+        rc = run(ps.upd, buf, C_dev, ps.k_begin);
+        if (rc != STTSM_OK) return rc;
+    }
+    return STTSM_OK;
+}
+
 int sttsm_profile_enable(int32_t max_launches)
 {
     if (max_launches < 1 || max_launches > (1 << 16)) return fail(STTSM_EINVAL, "max_launches must be 1..65536");

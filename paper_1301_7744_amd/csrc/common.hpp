@@ -117,6 +117,9 @@ struct StageArgs {
     // Block-copy FP32 kernel: one zero input block, read in place of the
     // blocks past nbar that a last, partial K chunk covers.
     const float *zero_blk;
+    // Generic kernel with an fp32 output: 1 adds the tile's sums to what the
+    // output holds (the rank-update form's passes after the first), 0 stores.
+    int32_t accumulate;
 };
 
 

@@ -748,7 +748,7 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
                 const int64_t np = s_npart[nn];
                 if (op >= 0 && np >= 0) {
                     const int64_t o = np + op;
-                    if (a.out_f32) out32[o] = acc[i][j][r];
+                    if (a.out_f32) out32[o] = a.accumulate ? out32[o] + acc[i][j][r] : acc[i][j][r];
                     else out16[o] = f2bf(acc[i][j][r]);
                 }
             }

@@ -827,6 +827,149 @@ namespace {
 std::map<std::tuple<int, int, int, int, bool>, std::unique_ptr<VecPlan>> g_vec;   // (device, m, nbar, b, upload)
 }
 
+bool rank_plan_build_host(const Plan &P, int rows, RankPlan *R, std::string *err)
+{
+    const int m = P.m;
+    if (m < 2 || (int)P.stages.size() != m) {
+        *err = "the rank-update form needs m >= 2";
+        return false;
+    }
+    for (const StagePlan &S : P.stages)
+        if (S.fast || S.fast_bf16) {
+            *err = "the rank-update form runs on the generic kernels";
+            return false;
+        }
+    if (rows < 1) {
+        *err = "rows per pass must be >= 1";
+        return false;
+    }
+    const int nbar = P.nbar;
+    const int S = std::min(rows, nbar);
+    const StagePlan &L = P.stages[m - 2];   // contracts mode 1, writes T^(1)
+    const StagePlan &U = P.stages[m - 1];   // contracts mode 0, writes C
+    const int64_t blk = P.temp_block[1];    // a T^(1) block: bA * bC^(m-1) entries
+    const int esz = P.temp_dtype[1] == F32 ? 4 : 2;
+    R->rows = S;
+    R->passes.clear();
+    // T^(1) is the last region of the chain's workspace; the pass buffer
+    // takes its place.
+    R->buf_off = P.temp_off[1];
+    R->buf_elems = P.temp_jtuples[1] * S * blk;
+    R->ws_bytes = (size_t)R->buf_off + (size_t)round_up(R->buf_elems * esz, 256);
+    for (int a0 = 0; a0 < nbar; a0 += S) {
+        const int Sc = std::min(S, nbar - a0);
+        RankPass ps;
+        ps.k_begin = (int64_t)a0 * P.bA;
+        // Row level.  Its groups are (trailing tuple, prefix i0), numbered
+        // jp * nbar + i0, with T^(1) block (jrank, i0) at (jrank * nbar + i0)
+        // blocks; in the pass buffer it sits at (jrank * Sc + i0 - a0).
+        StagePlan &row = ps.row;
+        row.d = L.d;
+        row.k = L.k;
+        row.compute = L.compute;
+        row.tile = L.tile;
+        row.args = L.args;
+        row.in_ws = L.in_ws;
+        row.xp_slot = L.xp_slot;
+        row.xp_lo_slot = L.xp_lo_slot;
+        std::vector<int32_t> remap(L.groups.size(), -1);
+        for (size_t gi = 0; gi < L.groups.size(); ++gi) {
+            const int i0 = (int)(gi % nbar);
+            if (i0 < a0 || i0 >= a0 + Sc) continue;
+            GroupDesc g = L.groups[gi];
+            const int64_t jr = (g.out_base / blk - i0) / nbar;
+            g.out_base = (jr * Sc + (i0 - a0)) * blk;
+            g.out_jstride = (int64_t)Sc * blk;
+            remap[gi] = (int32_t)row.groups.size();
+            row.groups.push_back(g);
+            row.flops += 2 * P.Kpad * (int64_t)L.args.Mblk * g.jcount * P.bC;
+        }
+        for (const Task &t : L.tasks) {
+            if (remap[t.group] < 0) continue;
+            Task u = t;
+            u.group = remap[t.group];
+            row.tasks.push_back(u);
+        }
+        row.args.ntasks = (int32_t)row.tasks.size();
+        // Update level: every C group, its input table cut to the pass's
+        // contracted blocks a0 .. a0+Sc-1 and rebased onto the pass buffer;
+        // X is read from column k_begin on.
+        StagePlan &upd = ps.upd;
+        upd.d = U.d;
+        upd.k = U.k;
+        upd.compute = U.compute;
+        upd.tile = U.tile;
+        upd.args = U.args;
+        upd.xp_slot = U.xp_slot;
+        upd.xp_lo_slot = U.xp_lo_slot;
+        for (const GroupDesc &g0 : U.groups) {
+            GroupDesc g = g0;
+            g.in_row = (int32_t)upd.in_tab.size();
+            upd.groups.push_back(g);
+            for (int ib = a0; ib < a0 + Sc; ++ib) {
+                InEntry e = U.in_tab[(size_t)g0.in_row + ib];
+                const int64_t jr = (e.off / blk - ib) / nbar;
+                e.off = (jr * Sc + (ib - a0)) * blk;
+                upd.in_tab.push_back(e);
+            }
+            upd.flops += 2 * (int64_t)Sc * P.bA * U.args.Mblk * g.jcount * P.bC;
+        }
+        upd.tasks = U.tasks;
+        StageArgs &ua = upd.args;
+        ua.nbar = Sc;
+        ua.Kpad = Sc * P.bA;
+        ua.nchunks = ua.chunk_blocks > 1 ? (Sc + ua.chunk_blocks - 1) / ua.chunk_blocks : Sc * ua.chunks_per_blk;
+        ua.accumulate = a0 > 0;
+        ua.ntasks = (int32_t)upd.tasks.size();
+        R->passes.push_back(std::move(ps));
+    }
+    return true;
+}
+
+struct RankKey {
+    DevKey dk;
+    int rows;
+    bool operator<(const RankKey &o) const { return rows != o.rows ? rows < o.rows : dk < o.dk; }
+};
+static std::map<RankKey, std::unique_ptr<RankPlan>> g_rank;
+
+const RankPlan *rank_plan_get(const PlanKey &key0, int rows, std::string *err)
+{
+    PlanKey key = key0;
+    key.generic_only = true;
+    key.grouped = false;
+    const Plan *P = plan_get(key, err);
+    if (!P) return nullptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        *err = "hipGetDevice failed";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    const RankKey rk{DevKey{dev, key}, std::max(rows, 0)};
+    auto it = g_rank.find(rk);
+    if (it != g_rank.end()) return it->second.get();
+    std::unique_ptr<RankPlan> R(new RankPlan);
+    if (!rank_plan_build_host(*P, rows, R.get(), err)) return nullptr;
+    R->chain = P;
+    const StagePlan &L = P->stages[P->m - 2];
+    for (RankPass &ps : R->passes) {
+        if (!upload(ps.row.groups, &ps.row.d_groups, err) || !upload(ps.row.tasks, &ps.row.d_tasks, err) ||
+            !upload(ps.upd.groups, &ps.upd.d_groups, err) || !upload(ps.upd.in_tab, &ps.upd.d_in_tab, err) ||
+            !upload(ps.upd.tasks, &ps.upd.d_tasks, err))
+            return nullptr;   // tables of a failed plan are leaked, never used
+        ps.row.args.groups = ps.row.d_groups;
+        ps.row.args.in_tab = L.d_in_tab;   // the row level reads T^(2) (or A) as the chain does
+        ps.row.args.tasks = ps.row.d_tasks;
+        ps.upd.args.groups = ps.upd.d_groups;
+        ps.upd.args.in_tab = ps.upd.d_in_tab;
+        ps.upd.args.tasks = ps.upd.d_tasks;
+    }
+    const RankPlan *out = R.get();
+    g_rank.emplace(rk, std::move(R));
+    return out;
+}
+
 const VecPlan *vec_plan_get(int m, int nbar, int b, bool upload, std::string *err)
 {
     int dev = 0;

@@ -92,6 +92,35 @@ const Plan *plan_get(const PlanKey &key, std::string *err);
 // stages split tail tiles so that no CU gets more than one half tile extra).
 bool plan_build_host(const PlanKey &key, Plan *out, std::string *err, int cus = 256);
 
+// Rank-update form of the operation (the second algorithmic variant of §8,
+// stated there for m = 2 as C = sum_i X_i (A_i X^T)): with Y = A x_1 X ...
+// x_{m-1} X (every mode but mode 0; its row i is row i of A times X in the
+// other modes), C = sum over the block rows i of Y of X_{:,i} x_0 Y_i.  The
+// block rows are taken in passes of `rows`: a pass forms its rows of Y (the
+// last temporary level restricted to the pass's prefixes) into a buffer of
+// one pass, then adds their rank-(rows * bA) update to C (the last level over
+// the pass's K range; the first pass stores, later passes add, in pass
+// order).  Levels above run as in the chain.  Every level uses the generic
+// staging kernel.
+struct RankPass {
+    StagePlan row;       // level m-2 restricted to the pass's prefixes, writing the pass buffer
+    StagePlan upd;       // level m-1 over the pass's rows only
+    int64_t k_begin = 0; // first contracted index of the pass (pass start * bA)
+};
+struct RankPlan {
+    const Plan *chain = nullptr;   // generic-kernel chain plan: X panels and levels 0..m-3
+    int rows = 0;                  // block rows per pass
+    std::vector<RankPass> passes;
+    int64_t buf_off = 0;           // the pass buffer in the workspace
+    int64_t buf_elems = 0;
+    size_t ws_bytes = 0;
+};
+// Host part from a host-built chain plan (generic kernels, m >= 2), for size
+// queries; rank_plan_get builds it over the cached chain plan and uploads its
+// tables.  rows >= nbar gives one pass.
+bool rank_plan_build_host(const Plan &chain, int rows, RankPlan *out, std::string *err);
+const RankPlan *rank_plan_get(const PlanKey &key, int rows, std::string *err);
+
 // Meta-data tensor of App. B for an order-m BCSS with nbar blocks per mode:
 // for every block t (dimensional order over nbar^m) the rank of sort(t) and a
 // permutation id; perm_strides[id*m + j] is the stride, inside the stored

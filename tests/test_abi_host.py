@@ -159,3 +159,36 @@ def test_vector_work_count(m, n, b, V):
     distinct = sum(len(set(t)) for t in itertools.combinations_with_replacement(range(nbar), m))
     assert st.sttsm_vectors_flops(m, n, b, V) == 2 * V * b ** m * distinct
     assert st.sttsm_vectors_flops(1, n, b, V) == -1
+
+
+@pytest.mark.parametrize("m,n,p,bA,bC", [(2, 100, 70, 16, 8), (3, 35, 20, 16, 8), (4, 13, 11, 3, 3)])
+def test_rank_update_workspace(m, n, p, bA, bC, monkeypatch):
+    """The rank-update form's workspace: the generic chain's, with T^(1)
+    (the last temporary) cut to the rows of one pass; one pass of all rows
+    needs exactly the chain's workspace."""
+    monkeypatch.setenv("STTSM_GENERIC_KERNELS", "1")
+    info = st.sttsm_workspace_temp(m, n, p, bA, bC, st.PREC_FP32, 1)
+    chain = st.sttsm_workspace_bytes(m, n, p, bA, bC, st.PREC_FP32)
+    nbar = -(-n // bA)
+    for rows in (1, 2, nbar, nbar + 5):
+        pass_bytes = info["num_jtuples"] * min(rows, nbar) * info["block_elems"] * 4
+        want = info["byte_offset"] + -(-pass_bytes // 256) * 256
+        assert st.sttsm_rank_update_workspace_bytes(m, n, p, bA, bC, st.PREC_FP32, rows) == want
+    assert st.sttsm_rank_update_workspace_bytes(m, n, p, bA, bC, st.PREC_FP32, nbar) == chain
+    monkeypatch.delenv("STTSM_GENERIC_KERNELS")
+    # independent of the kernel choice sttsm itself would make
+    assert st.sttsm_rank_update_workspace_bytes(m, n, p, bA, bC, st.PREC_FP32, nbar) == chain
+
+
+def test_rank_update_host_checks():
+    """m = 1 and rows < 1 are rejected before any launch."""
+    lib = st.load()
+    L1A, L1C = st.layout(1, 10, 4), st.layout(1, 6, 4)
+    assert lib.sttsm_rank_update_workspace_bytes(ctypes.byref(L1A), ctypes.byref(L1C), st.PREC_FP32, 1) == 0
+    rc = lib.sttsm_rank_update(ctypes.byref(L1A), 1, 1, 10, 1, ctypes.byref(L1C), 1, st.PREC_FP32, 1, None, 0, None)
+    assert rc == -1
+    LA, LC = st.layout(2, 10, 4), st.layout(2, 6, 4)
+    assert lib.sttsm_rank_update_workspace_bytes(ctypes.byref(LA), ctypes.byref(LC), st.PREC_FP32, 0) == 0
+    rc = lib.sttsm_rank_update(ctypes.byref(LA), 1, 1, 10, 1, ctypes.byref(LC), 1, st.PREC_FP32, 0, None, 0, None)
+    assert rc == -1
+    assert "rows" in lib.sttsm_last_error().decode()

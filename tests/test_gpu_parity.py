@@ -567,3 +567,65 @@ def test_vectors_vs_oracle(m, n, b, V, dt):
     say("vectors", m, n, b, V, dt, "rel err y", ey, "s", es)
     assert ey <= tol and es <= tol
     assert torch.equal(y, y2) and torch.equal(s, s2)
+
+
+# ------------------------------------------------------------------ rank-update form (§8, second variant)
+RANK_CASES = [(2, 37, 29, 8, 8, 1, P32), (2, 64, 64, 16, 16, 3, P32), (2, 100, 70, 16, 8, 2, PBF),
+              (2, 50, 50, 8, 8, 2, PX3F), (3, 23, 19, 4, 4, 2, P32), (3, 40, 40, 8, 8, 1, PBF),
+              (4, 13, 11, 3, 3, 2, P32), (2, 300, 200, 64, 64, 2, P32), (3, 35, 20, 16, 8, 5, P32)]
+
+
+def _rank_inputs(m, n, p, prec, seed):
+    import torch
+    A = synth.symmetric_uniform(m, n, (m, n, seed))
+    X = synth.change_of_basis(p, n, (m, n, seed + 1))
+    tdt = torch.float32
+    if prec == PBF:
+        A, X, tdt = synth.round_to_bf16(A), synth.round_to_bf16(X), torch.bfloat16
+    return A, X, tdt
+
+
+@pytest.mark.parametrize("case", RANK_CASES)
+def test_rank_update_vs_oracle(case):
+    """sttsm_rank_update against the oracle's rank-update form (passes of the
+    same size), over a C that starts as NaN: every entry is written, the
+    padding comes out exactly zero."""
+    import torch
+    m, n, p, bA, bC, rows, prec = case
+    say("rank-update", case)
+    A, X, tdt = _rank_inputs(m, n, p, prec, 91)
+    Ab = st().bcss_pack(dev_dense(np.asarray(A, np.float32), tdt), m, n, bA)
+    Xd = torch.from_numpy(np.ascontiguousarray(X, np.float32)).to(tdt).cuda()
+    nc = st().bcss_num_elems(m, p, bC)
+    C0 = torch.full((nc,), float("nan"), dtype=torch.float32, device="cuda")
+    C, _ = st().sttsm_rank_update(Ab, Xd, m, n, p, bA, bC, prec, rows, C=C0)
+    torch.cuda.synchronize()
+    got = C.double().cpu().numpy().reshape(-1, bC ** m)
+    ref = bcss_ref.pack(oracle.rank_update(A.astype(np.float64), X.astype(np.float64), bA, rows), bC)
+    e = err(got, ref, m, p, bC)
+    bound = {P32: TOL_FP32, PBF: tol_bf16(m), PX3F: TOL_X3_FIRST_FP32}[prec]
+    say("  rel err", e, "bound", bound)
+    assert e <= bound
+    assert np.all(got[padding_mask(m, p, bC)] == 0.0)
+
+
+@pytest.mark.parametrize("case", [(2, 100, 70, 16, 8, P32), (3, 35, 20, 16, 8, P32), (3, 40, 40, 8, 8, PBF),
+                                  (2, 300, 200, 64, 64, P32)])
+def test_rank_update_one_pass_is_the_chain(case, monkeypatch):
+    """One pass of every block row is the chain on the generic kernels, bit
+    for bit; several passes give the same bits on every call."""
+    import torch
+    m, n, p, bA, bC, prec = case
+    say("rank-update bitwise", case)
+    monkeypatch.setenv("STTSM_GENERIC_KERNELS", "1")
+    A, X, tdt = _rank_inputs(m, n, p, prec, 93)
+    Ab = st().bcss_pack(dev_dense(np.asarray(A, np.float32), tdt), m, n, bA)
+    Xd = torch.from_numpy(np.ascontiguousarray(X, np.float32)).to(tdt).cuda()
+    nbar = -(-n // bA)
+    C1, _ = st().sttsm(Ab, Xd, m, n, p, bA, bC, prec)
+    C2, _ = st().sttsm_rank_update(Ab, Xd, m, n, p, bA, bC, prec, nbar)
+    C3, ws = st().sttsm_rank_update(Ab, Xd, m, n, p, bA, bC, prec, 2)
+    C4, _ = st().sttsm_rank_update(Ab, Xd, m, n, p, bA, bC, prec, 2, ws=ws)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2)
+    assert torch.equal(C3, C4)

@@ -235,3 +235,44 @@ def test_vectors_rank_r(m, n, r):
     Yc, sc = closed_forms.rank_r_vectors(lams, vecs, X, m)
     assert rel(Y, Yc) <= 1e-12 and rel(s, sc) <= 1e-12
     assert rel(s, np.sum(X * Y, axis=1)) <= 1e-12
+
+
+# ---------------------------------------------------------------- rank-update form (§8, second variant)
+@pytest.mark.parametrize("n,p,b,rows", [(5, 3, 2, 1), (7, 7, 3, 2), (8, 6, 8, 1), (9, 4, 2, 3), (4, 6, 1, 1)])
+def test_rank_update_matrix_case(n, p, b, rows):
+    """m = 2: the sum of the rank-b updates X_i (A_i X^T) over the block
+    rows is X A X^T (library matrix products), for any pass size,
+    including a ragged last block."""
+    A = sym(2, n, 81)
+    X = synth.change_of_basis(p, n, 82).astype(np.float64)
+    assert rel(oracle.rank_update(A, X, b, rows), closed_forms.matrix_case(A, X)) <= TOL
+
+
+@pytest.mark.parametrize("m,n,p,b,rows", [(3, 4, 3, 2, 1), (3, 5, 5, 2, 2), (4, 3, 2, 1, 2), (4, 4, 3, 3, 1)])
+def test_rank_update_equals_direct_sum(m, n, p, b, rows):
+    """Order m: the rank-update form equals the literal sum of §2.5."""
+    A = sym(m, n, 83)
+    X = synth.change_of_basis(p, n, 84).astype(np.float64)
+    assert rel(oracle.rank_update(A, X, b, rows), oracle.direct_sum(A, X)) <= TOL
+
+
+@pytest.mark.parametrize("m,n,p,r", [(3, 6, 4, 2), (4, 5, 3, 3)])
+def test_rank_update_rank_r(m, n, p, r):
+    """Rank-r A: the rank-update form equals sum_i lam_i (X a_i)^{o m}."""
+    lams, vecs = synth.rank_r_factors(n, r, 85)
+    A = synth.rank_r_symmetric(m, lams, vecs)
+    X = synth.change_of_basis(p, n, 86).astype(np.float64)
+    assert rel(oracle.rank_update(A, X, 2, 1), closed_forms.rank_r(lams, vecs, X, m)) <= 1e-12
+
+
+def test_rank_update_misses_a_row_block_fails_the_pin():
+    """A form that skipped the last block row (a plausible pass-boundary
+    mistake) fails the matrix-case pin."""
+    n, p, b = 7, 5, 3
+    A = sym(2, n, 87)
+    X = synth.change_of_basis(p, n, 88).astype(np.float64)
+    Y = oracle.all_but_one(A, X)
+    C = np.zeros((p, p))
+    for i0 in range(0, n - n % b, b):   # drops the ragged tail block
+        C += X[:, i0:i0 + b] @ Y[i0:i0 + b]
+    assert rel(C, closed_forms.matrix_case(A, X)) > 1e-3
