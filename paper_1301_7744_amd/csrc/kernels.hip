@@ -542,6 +542,7 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
 
     __syncthreads();
 
+    int in_mm[IN_PER_T], in_kv[IN_PER_T];   // row and k vector of each staged input vector
     auto load_chunk = [&](int c) {
         const int blk0 = (c / a.chunks_per_blk) * a.chunk_blocks;
         const int lk0 = (c % a.chunks_per_blk) * a.chunk_k;
@@ -550,31 +551,87 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
         if (a.chunk_blocks > 1) kvalid = min(a.chunk_blocks, a.nbar - blk0) * a.bA;
         else kvalid = min(a.chunk_k, a.bA - lk0);
         const int kstart = blk0 * a.bA + lk0;
+        if (a.chunk_blocks == 1) {
+            // The chunk lies inside one input block: one table entry, one
+            // permutation and one stride of the contracted mode for all of
+            // it.  Threads run along k when the contracted mode is stored
+            // fastest, else along the rows, so that neighbouring threads
+            // read neighbouring entries either way; whole aligned vectors
+            // along k are read as 16-byte loads.
+            int64_t ioff;
+            int iq;
+            if (tab_lds) {
+                ioff = sm.s_ioff[blk0];
+                iq = sm.s_iq[blk0];
+            } else {
+                const InEntry ie = row[blk0];
+                ioff = ie.off;
+                iq = ie.q;
+            }
+            const int sk = sm.s_sqk[iq];
+            const bool kfast = sk == 1;
 #pragma unroll
-        for (int t = 0; t < IN_PER_T; ++t) {
-            const int v = tid + t * 256;
-            const int mm = v % MT, kv = v / MT;
+            for (int t = 0; t < IN_PER_T; ++t) {
+                const int v = tid + t * 256;
+                const int mm = kfast ? v / (KT / VK) : v % MT;
+                const int kv = kfast ? v % (KT / VK) : v / MT;
+                in_mm[t] = mm;
+                in_kv[t] = kv;
 #pragma unroll
-            for (int e = 0; e < VK; ++e) in_f[t][e] = 0.f;
-            if (v < IN_VECS && s_mpart[0][mm] >= 0) {
+                for (int e = 0; e < VK; ++e) in_f[t][e] = 0.f;
+                if (v < IN_VECS && s_mpart[0][mm] >= 0) {
+                    const int64_t off = ioff + s_mpart[iq][mm] + (int64_t)(lk0 + kv * VK) * sk;
+                    const bool whole = kfast && kv * VK + VK <= kvalid;
+                    if (whole && a.in_f32 && ((uintptr_t)(in32 + off) & 15) == 0) {
 #pragma unroll
-                for (int e = 0; e < VK; ++e) {
-                    const int kk = kv * VK + e;
-                    if (kk < kvalid) {
-                        const int gi = kk / a.chunk_k;
-                        const int lk = lk0 + (kk - gi * a.chunk_k);
-                        int64_t ioff;
-                        int iq;
-                        if (tab_lds) {
-                            ioff = sm.s_ioff[blk0 + gi];
-                            iq = sm.s_iq[blk0 + gi];
-                        } else {
-                            const InEntry ie = row[blk0 + gi];
-                            ioff = ie.off;
-                            iq = ie.q;
+                        for (int h = 0; h < VK / 4; ++h) {
+                            const f32x4 w = *(const f32x4 *)(in32 + off + 4 * h);
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) in_f[t][4 * h + e] = w[e];
                         }
-                        const int64_t off = ioff + s_mpart[iq][mm] + (int64_t)lk * sm.s_sqk[iq];
-                        in_f[t][e] = a.in_f32 ? in32[off] : bf2f(in16[off]);
+                    } else if (VK == 8 && whole && !a.in_f32 && ((uintptr_t)(in16 + off) & 15) == 0) {
+                        const u16x8 w = *(const u16x8 *)(in16 + off);
+#pragma unroll
+                        for (int e = 0; e < VK; ++e) in_f[t][e] = bf2f(w[e & 7]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VK; ++e)
+                            if (kv * VK + e < kvalid) {
+                                const int64_t o = off + (int64_t)e * sk;
+                                in_f[t][e] = a.in_f32 ? in32[o] : bf2f(in16[o]);
+                            }
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < IN_PER_T; ++t) {
+                const int v = tid + t * 256;
+                const int mm = v % MT, kv = v / MT;
+                in_mm[t] = mm;
+                in_kv[t] = kv;
+#pragma unroll
+                for (int e = 0; e < VK; ++e) in_f[t][e] = 0.f;
+                if (v < IN_VECS && s_mpart[0][mm] >= 0) {
+#pragma unroll
+                    for (int e = 0; e < VK; ++e) {
+                        const int kk = kv * VK + e;
+                        if (kk < kvalid) {
+                            const int gi = kk / a.chunk_k;
+                            const int lk = lk0 + (kk - gi * a.chunk_k);
+                            int64_t ioff;
+                            int iq;
+                            if (tab_lds) {
+                                ioff = sm.s_ioff[blk0 + gi];
+                                iq = sm.s_iq[blk0 + gi];
+                            } else {
+                                const InEntry ie = row[blk0 + gi];
+                                ioff = ie.off;
+                                iq = ie.q;
+                            }
+                            const int64_t off = ioff + s_mpart[iq][mm] + (int64_t)lk * sm.s_sqk[iq];
+                            in_f[t][e] = a.in_f32 ? in32[off] : bf2f(in16[off]);
+                        }
                     }
                 }
             }
@@ -586,13 +643,18 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
             const int ng = n0 + nn;
             const bool rowok = v < X_VECS && ng < Nvalid;
             const int64_t base = (int64_t)ng * a.Kx + kstart + kv * VK;
+            const bool xwhole = kv * VK + VK <= kvalid;
             if constexpr (CMP == CMP_FP32) {
                 const float *xp = (const float *)a.xp;
                 f32x4 val = {0.f, 0.f, 0.f, 0.f};
                 if (rowok) {
+                    if (xwhole && ((uintptr_t)(xp + base) & 15) == 0) {
+                        val = *(const f32x4 *)(xp + base);
+                    } else {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (kv * 4 + e < kvalid) val[e] = xp[base + e];
+                        for (int e = 0; e < 4; ++e)
+                            if (kv * 4 + e < kvalid) val[e] = xp[base + e];
+                    }
                 }
                 x_f32[t] = val;
             } else {
@@ -600,11 +662,17 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
                 const u16 *xl = (const u16 *)a.xp_lo;
                 u16x8 h = {0, 0, 0, 0, 0, 0, 0, 0}, l = {0, 0, 0, 0, 0, 0, 0, 0};
                 if (rowok) {
+                    if (xwhole && ((uintptr_t)(xh + base) & 15) == 0 &&
+                        (!SPLIT || ((uintptr_t)(xl + base) & 15) == 0)) {
+                        h = *(const u16x8 *)(xh + base);
+                        if constexpr (SPLIT) l = *(const u16x8 *)(xl + base);
+                    } else {
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        if (kv * 8 + e < kvalid) {
-                            h[e] = xh[base + e];
-                            if constexpr (SPLIT) l[e] = xl[base + e];
+                        for (int e = 0; e < 8; ++e) {
+                            if (kv * 8 + e < kvalid) {
+                                h[e] = xh[base + e];
+                                if constexpr (SPLIT) l[e] = xl[base + e];
+                            }
                         }
                     }
                 }
@@ -619,7 +687,7 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
         for (int t = 0; t < IN_PER_T; ++t) {
             const int v = tid + t * 256;
             if (v >= IN_VECS) break;
-            const int mm = v % MT, kv = v / MT;
+            const int mm = in_mm[t], kv = in_kv[t];
             if constexpr (CMP == CMP_FP32) {
                 f32x4 val = {in_f[t][0], in_f[t][1], in_f[t][2], in_f[t][3]};
                 *(f32x4 *)&s_in[0][buf][mm * LROW + kv * 4] = val;

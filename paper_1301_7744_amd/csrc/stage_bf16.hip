@@ -66,19 +66,21 @@ template <int M, int B, int K, int NT, int KT>
 struct Bf16Cfg {
     static constexpr int MT = B * B;
     static constexpr bool KM = K == 0;                  // LDS [row][kk] (else [kk][row])
-    // One block per chunk (b = 16, K chunk 16) below the last level: a
-    // chunk whose block has its contracted mode stored fastest (q = 0) is
-    // staged as [row][kk] instead, so no entry is ever written transposed.
-    static constexpr bool DUAL = !KM && KT == B;
+    // b = 16 below the last level: each 16-wide k step of a chunk is one
+    // whole block, staged in a region of its own; a block whose contracted
+    // mode is stored fastest (q = 0) is staged there as [row][kk], any other
+    // as [kk][row], so no entry is ever written transposed.
+    static constexpr bool DUAL = !KM && B == 16;
     static constexpr int RS = MT + 16;                  // [kk][row] row stride (bf16)
-    static constexpr int RSK = KT + 8;                  // [row][kk] row stride
+    static constexpr int RSK = DUAL ? B + 8 : KT + 8;   // [row][kk] row stride (of one block's region if DUAL)
+    static constexpr int REG = B * RS > MT * RSK ? B * RS : MT * RSK;   // one block's region (DUAL)
     static constexpr int XS = KT + 8;                   // X [nn][kk] row stride
-    static constexpr int IN_ELEMS = KM ? MT * RSK : (DUAL ? (KT * RS > MT * RSK ? KT * RS : MT * RSK) : KT * RS);
     // waves along M: 4 for 32-wide column tiles, else 2 (1 for 64-row tiles)
     static constexpr int WM = NT <= 32 ? 4 : (MT >= 128 ? 2 : 1), WN = 4 / WM;
     static constexpr int WTM = MT / WM, WTN = NT / WN;
     static constexpr int TM = WTM / 32, TN = WTN / 32;
     static constexpr int G = KT / B;                    // whole blocks per K chunk
+    static constexpr int IN_ELEMS = KM ? MT * RSK : (DUAL ? G * REG : KT * RS);
     static constexpr int PART = B * B * B / 8;          // 16-byte vectors of one block's tile part
     static constexpr int VEC = G * PART;                // ... per chunk
     static constexpr int NV = (VEC + 255) / 256;        // per thread
@@ -87,6 +89,7 @@ struct Bf16Cfg {
     static_assert(KT % B == 0 && KT % 16 == 0, "chunk");
     static_assert(TM >= 1 && TN >= 1, "tile");
     static_assert(PART % 64 == 0, "a block part spans whole waves");
+    static_assert(!DUAL || PART % 256 == 0, "DUAL: a thread's f-th vector lies in block 256 f / PART");
 };
 
 constexpr int kOutRow = 40;   // row stride (bf16) of a wave's 32 x 32 output staging tile
@@ -202,7 +205,7 @@ __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, B
     u32x4 rin[PD][NV], rx[PD][NXV];
     int rl[PD][NV];
     bool rk[PD][NV], rv[PD][NV], rxv[PD][NXV];
-    bool rkm[PD];   // DUAL: the chunk's block is staged [row][kk]
+    bool rkm[PD][G];   // DUAL: block g of the chunk is staged [row][kk]
     auto load_chunk = [&](int c, int u) {
 #pragma unroll
         for (int f = 0; f < NV; ++f) {
@@ -215,7 +218,7 @@ __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, B
             const int q = __builtin_amdgcn_readfirstlane(sm.s_iq[ibc]);
             int goff = 0, loff = 0;
             bool ak = false;
-            const int kb = vg[f] * B;
+            const int kb = C::DUAL ? 0 : vg[f] * B;   // DUAL: offset inside the block's region
             switch (q) {
 #define STTSM_Q(QQ) \
     case QQ: \
@@ -226,10 +229,12 @@ __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, B
 #undef STTSM_Q
             default: break;
             }
+            if constexpr (C::DUAL) loff += vg[f] * C::REG;
             rl[u][f] = loff;
             rk[u][f] = ak;
             rv[u][f] = valid;
-            if (f == 0) rkm[u] = C::DUAL && q == 0;
+            if constexpr (C::DUAL)
+                if ((256 * f) % PART == 0) rkm[u][(256 * f) / PART] = q == 0;
             rin[u][f] = *(const u32x4 *)(in + sm.s_ioff[ibc] + goff);
         }
 #pragma unroll
@@ -288,23 +293,28 @@ __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, B
     auto mfma_chunk = [&](int buf, int c, int u) {
         const u16 *si = sm.s_in[buf];
         const u16 *sx = sm.s_x[buf];
-        const bool km = C::KM || (C::DUAL && rkm[u]);   // read before stage u is reloaded
+        bool kmv[KT / 16];   // read before stage u is reloaded
+#pragma unroll
+        for (int s = 0; s < KT / 16; ++s) kmv[s] = C::KM || (C::DUAL && rkm[u][s]);
 #pragma unroll
         for (int s = 0; s < KT / 16; ++s) {
             bf16x8 va[TM], vb[TN];
+            // k step s: block s's region (DUAL), else columns 16 s .. 16 s + 15
+            const int sbase = C::DUAL ? s * C::REG : 0, sk = C::DUAL ? 0 : 16 * s;
             if (wave_live) {
 #pragma unroll
                 for (int i = 0; i < TM; ++i) {
                     const int rb = wm * WTM + 32 * i;
-                    if (km) {
-                        va[i] = __builtin_bit_cast(bf16x8, *(const u16x8 *)&si[(rb + r32) * RSK + 16 * s + 8 * half]);
+                    if (kmv[s]) {
+                        va[i] = __builtin_bit_cast(bf16x8,
+                                                   *(const u16x8 *)&si[sbase + (rb + r32) * RSK + sk + 8 * half]);
                     } else {
                         // Lane 4t + u of a 16-lane group points at row kk0 + t,
                         // entries rbase + 4u .. +3; the transposing read hands
                         // lane i of the group entries (rbase + i, kk0 .. kk0+3).
-                        const int kk0 = 16 * s + 8 * (grp >> 1);
+                        const int kk0 = sk + 8 * (grp >> 1);
                         const int rbase = rb + 16 * (grp & 1);
-                        const int o = (kk0 + (gl >> 2)) * RS + rbase + 4 * (gl & 3);
+                        const int o = sbase + (kk0 + (gl >> 2)) * RS + rbase + 4 * (gl & 3);
                         typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
                         const s16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(si + o));
                         const s16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(si + o + 4 * RS));

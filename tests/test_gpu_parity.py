@@ -432,6 +432,30 @@ def test_bf16_block_copy_and_generic_kernels(m, n, p, b, generic, monkeypatch):
     assert np.all(got[padding_mask(m, p, b)] == 0.0)
 
 
+# bf16 tile variants (STTSM_BF16_TILE, "NTxKTxPD" per level): 32-wide K chunks
+# hold two b = 16 blocks, each staged in its own region with its own layout.
+# Plans are cached per shape, so every case has a shape no other test uses.
+BF16_TILE_CASES = [("64x32x1", 3, 101, 69, 16), ("64x32x2,128x32x1,64x32x2", 3, 131, 61, 16),
+                   ("128x32x1", 4, 41, 36, 16), ("64x16x3,64x16x1,32x16x1", 3, 36, 34, 16),
+                   ("128x32x2,256x32x1,128x16x3", 3, 41, 23, 8)]
+
+
+@pytest.mark.parametrize("tiles,m,n,p,b", BF16_TILE_CASES, ids=[c[0] for c in BF16_TILE_CASES])
+def test_bf16_tile_variants(tiles, m, n, p, b, monkeypatch):
+    """Each bf16 block-copy tile variant against the oracle on a ragged shape."""
+    import torch
+    monkeypatch.delenv("STTSM_GENERIC_KERNELS", raising=False)
+    monkeypatch.setenv("STTSM_BF16_TILE", tiles)
+    say("bf16 tile variant", tiles, m, n, p, b)
+    A = synth.round_to_bf16(synth.symmetric_uniform(m, n, (m, n, p, 95)))
+    X = synth.round_to_bf16(synth.change_of_basis(p, n, (m, n, p, 96)))
+    got = run(A, X, b, b, PBF, dtype=torch.bfloat16)
+    e = err(got, ref_bcss(A.astype(np.float64), X.astype(np.float64), b), m, p, b)
+    say("  rel err", e, "bound", tol_bf16(m))
+    assert e <= tol_bf16(m)
+    assert np.all(got[padding_mask(m, p, b)] == 0.0)
+
+
 def test_bf16_block_copy_config2_full():
     """m = 3, n = p = 256, b = 16 in bf16 through the block-copy kernel (the
     bench workload at bf16): the whole C against the oracle chain on the same
