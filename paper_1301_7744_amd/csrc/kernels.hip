@@ -603,6 +603,56 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
                     }
                 }
             }
+        } else if (a.bA % VK == 0) {
+            // Several whole blocks per chunk, bA a multiple of VK: a
+            // vector's VK k values lie in one block, so it takes one table
+            // entry, and one 16-byte load where the contracted mode is
+            // stored fastest.  kvalid is a multiple of bA, so a vector is
+            // either wholly valid or wholly past the end.
+#pragma unroll
+            for (int t = 0; t < IN_PER_T; ++t) {
+                const int v = tid + t * 256;
+                const int mm = v % MT, kv = v / MT;
+                in_mm[t] = mm;
+                in_kv[t] = kv;
+#pragma unroll
+                for (int e = 0; e < VK; ++e) in_f[t][e] = 0.f;
+                const int kk0 = kv * VK;
+                if (v < IN_VECS && s_mpart[0][mm] >= 0 && kk0 < kvalid) {
+                    const int gi = kk0 / a.chunk_k;
+                    const int lk = lk0 + (kk0 - gi * a.chunk_k);
+                    int64_t ioff;
+                    int iq;
+                    if (tab_lds) {
+                        ioff = sm.s_ioff[blk0 + gi];
+                        iq = sm.s_iq[blk0 + gi];
+                    } else {
+                        const InEntry ie = row[blk0 + gi];
+                        ioff = ie.off;
+                        iq = ie.q;
+                    }
+                    const int sk = sm.s_sqk[iq];
+                    const int64_t off = ioff + s_mpart[iq][mm] + (int64_t)lk * sk;
+                    if (sk == 1 && a.in_f32 && ((uintptr_t)(in32 + off) & 15) == 0) {
+#pragma unroll
+                        for (int h = 0; h < VK / 4; ++h) {
+                            const f32x4 w = *(const f32x4 *)(in32 + off + 4 * h);
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) in_f[t][4 * h + e] = w[e];
+                        }
+                    } else if (VK == 8 && sk == 1 && !a.in_f32 && ((uintptr_t)(in16 + off) & 15) == 0) {
+                        const u16x8 w = *(const u16x8 *)(in16 + off);
+#pragma unroll
+                        for (int e = 0; e < VK; ++e) in_f[t][e] = bf2f(w[e & 7]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VK; ++e) {
+                            const int64_t o = off + (int64_t)e * sk;
+                            in_f[t][e] = a.in_f32 ? in32[o] : bf2f(in16[o]);
+                        }
+                    }
+                }
+            }
         } else {
 #pragma unroll
             for (int t = 0; t < IN_PER_T; ++t) {
