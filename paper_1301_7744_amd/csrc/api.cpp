@@ -351,7 +351,7 @@ int run_levels(const bcss_layout *A, const void *A_dev, const void *X_dev, int64
         if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot], s);
         const int lrc = S.fast_bf16 ? launch_stage_bf16(a, S.tile.NT, S.tile.KT, S.tile.PD, s)
                         : S.fast  ? launch_stage_fast(a, S.tile.MT, S.tile.NT, S.tile.KT, S.tile.PD, S.d == 0, s)
-                                  : launch_stage(a, S.compute, S.tile.MT, S.d == 0, s);
+                                  : launch_stage(a, S.compute, S.tile.MT, S.tile.NT, S.d == 0, s);
         if (lrc)
             return fail(STTSM_EHIP, std::string("stage launch failed: ") + hipGetErrorString(hipGetLastError()));
         if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot + 1], s);
@@ -452,7 +452,7 @@ int sttsm_rank_update(const bcss_layout *A, const void *A_dev, const void *X_dev
         if (!a.xp || (S.xp_lo_slot >= 0 && !a.xp_lo)) return fail(STTSM_EINVAL, "X panel missing from the plan");
         const long slot = prof_slot(S.d);
         if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot], s);
-        if (launch_stage(a, S.compute, S.tile.MT, S.d == 0, s))
+        if (launch_stage(a, S.compute, S.tile.MT, S.tile.NT, S.d == 0, s))
             return fail(STTSM_EHIP, std::string("stage launch failed: ") + hipGetErrorString(hipGetLastError()));
         if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot + 1], s);
         return STTSM_OK;

@@ -927,9 +927,17 @@ int launch_grouped(int compute, const StageArgs *d_stages, const GroupedTask *d_
 // FIRST marks the level that reads A; it is a separate instantiation so that
 // profilers report the first contraction on its own.
 template <int CMP, bool B_IS_IN, bool FIRST>
-static int launch_stage_cmp(const StageArgs &a, int MT, hipStream_t s)
+static int launch_stage_cmp(const StageArgs &a, int MT, int NT, hipStream_t s)
 {
     const dim3 grid((unsigned)a.ntasks), block(256);
+    if (NT == 32) {   // narrow groups (few output columns): four waves along the rows
+        switch (MT) {
+        case 256: hipLaunchKernelGGL((stage_kernel<CMP, 256, 32, 4, 1, B_IS_IN, FIRST>), grid, block, 0, s, a); break;
+        case 128: hipLaunchKernelGGL((stage_kernel<CMP, 128, 32, 4, 1, B_IS_IN, FIRST>), grid, block, 0, s, a); break;
+        default: return -1;
+        }
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+    }
     switch (MT) {
     case 256: hipLaunchKernelGGL((stage_kernel<CMP, 256, 64, 4, 1, B_IS_IN, FIRST>), grid, block, 0, s, a); break;
     case 128: hipLaunchKernelGGL((stage_kernel<CMP, 128, 64, 2, 2, B_IS_IN, FIRST>), grid, block, 0, s, a); break;
@@ -941,21 +949,23 @@ static int launch_stage_cmp(const StageArgs &a, int MT, hipStream_t s)
 }
 
 template <int CMP>
-static int launch_stage_c(const StageArgs &a, int MT, bool first, hipStream_t s)
+static int launch_stage_c(const StageArgs &a, int MT, int NT, bool first, hipStream_t s)
 {
     const bool b_in = a.k != 0;   // output contiguous along the block rows unless mode 0 is contracted
-    if (first) return b_in ? launch_stage_cmp<CMP, true, true>(a, MT, s) : launch_stage_cmp<CMP, false, true>(a, MT, s);
-    return b_in ? launch_stage_cmp<CMP, true, false>(a, MT, s) : launch_stage_cmp<CMP, false, false>(a, MT, s);
+    if (first)
+        return b_in ? launch_stage_cmp<CMP, true, true>(a, MT, NT, s) : launch_stage_cmp<CMP, false, true>(a, MT, NT, s);
+    return b_in ? launch_stage_cmp<CMP, true, false>(a, MT, NT, s) : launch_stage_cmp<CMP, false, false>(a, MT, NT, s);
 }
 
-int launch_stage(const StageArgs &a, int compute, int MT, bool first, hipStream_t s)
+int launch_stage(const StageArgs &a, int compute, int MT, int NT, bool first, hipStream_t s)
 {
     if (a.ntasks <= 0) return 0;
-    if (compute == CMP_FP32) return launch_stage_c<CMP_FP32>(a, MT, first, s);
-    if (compute == CMP_BF16) return launch_stage_c<CMP_BF16>(a, MT, first, s);
+    if (compute == CMP_FP32) return launch_stage_c<CMP_FP32>(a, MT, NT, first, s);
+    if (compute == CMP_BF16) return launch_stage_c<CMP_BF16>(a, MT, NT, first, s);
     if (compute == CMP_X3) {   // the split form only ever runs the first level
         if (!first) return -1;
-        return a.k != 0 ? launch_stage_cmp<CMP_X3, true, true>(a, MT, s) : launch_stage_cmp<CMP_X3, false, true>(a, MT, s);
+        return a.k != 0 ? launch_stage_cmp<CMP_X3, true, true>(a, MT, NT, s)
+                        : launch_stage_cmp<CMP_X3, false, true>(a, MT, NT, s);
     }
     return -1;
 }

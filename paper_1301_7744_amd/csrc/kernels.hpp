@@ -16,7 +16,7 @@ int launch_fill_hashed(int esize, void *bcss, int m, int64_t n, int b, int64_t n
                        uint64_t seed, double lo, double hi, hipStream_t s);
 int launch_prep_x(int esize, const void *X, int64_t rs, int64_t cs, int64_t p, int64_t n, int64_t Ppad,
                   int64_t Kx, float *x32, uint16_t *xhi, uint16_t *xlo, hipStream_t s);
-int launch_stage(const StageArgs &a, int compute, int MT, bool first, hipStream_t s);
+int launch_stage(const StageArgs &a, int compute, int MT, int NT, bool first, hipStream_t s);
 int launch_stage_fast(const StageArgs &a, int MT, int NT, int KT, int PD, bool first, hipStream_t s);
 bool fast_tile_supported(int MT, int NT, int KT, int PD);
 // Grouped persistent launch over a task queue (*d_head must be 0).

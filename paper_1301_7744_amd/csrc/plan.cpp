@@ -510,6 +510,18 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err, int cus)
                 S.flops += 2 * P->Kpad * (int64_t)Mblk * jcount * bC;
             }
         }
+        // Generic kernel, narrow row groups (few output columns, as in the
+        // levels below the first and whenever p is small): 32-column tiles
+        // when they cut the padded columns by a quarter or more.
+        if (!key.grouped && !S.fast && !S.fast_bf16 && S.tile.MT >= 128) {
+            int64_t c32 = 0, c64 = 0;
+            for (const GroupDesc &g : S.groups) {
+                const int64_t N = (int64_t)g.jcount * bC;
+                c32 += (N + 31) / 32 * 32;
+                c64 += (N + 63) / 64 * 64;
+            }
+            if (4 * c32 <= 3 * c64) S.tile = TileCfg{S.tile.MT, 32, 4, 1};
+        }
         if (S.fast) {
             // Tile of the block-copy kernel.  Below the first level a tile may
             // take half a block row (split along mode m-1, contiguous in
