@@ -958,7 +958,7 @@ const RankPlan *rank_plan_get(const PlanKey &key0, int rows, std::string *err)
         return nullptr;
     }
     std::lock_guard<std::mutex> lock(g_plan_mu);
-    const RankKey rk{DevKey{dev, key}, std::max(rows, 0)};
+    const RankKey rk{DevKey{dev, key}, std::max(std::min(rows, P->nbar), 0)};   // rows >= nbar: one pass
     auto it = g_rank.find(rk);
     if (it != g_rank.end()) return it->second.get();
     std::unique_ptr<RankPlan> R(new RankPlan);

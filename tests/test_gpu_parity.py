@@ -648,8 +648,10 @@ def test_rank_update_one_pass_is_the_chain(case, monkeypatch):
     nbar = -(-n // bA)
     C1, _ = st().sttsm(Ab, Xd, m, n, p, bA, bC, prec)
     C2, _ = st().sttsm_rank_update(Ab, Xd, m, n, p, bA, bC, prec, nbar)
+    C2b, _ = st().sttsm_rank_update(Ab, Xd, m, n, p, bA, bC, prec, nbar + 3)   # more rows than there are
     C3, ws = st().sttsm_rank_update(Ab, Xd, m, n, p, bA, bC, prec, 2)
     C4, _ = st().sttsm_rank_update(Ab, Xd, m, n, p, bA, bC, prec, 2, ws=ws)
     torch.cuda.synchronize()
     assert torch.equal(C1, C2)
+    assert torch.equal(C1, C2b)
     assert torch.equal(C3, C4)
