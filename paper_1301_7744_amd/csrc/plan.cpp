@@ -67,9 +67,17 @@ bool PlanKey::operator<(const PlanKey &o) const
 
 static int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
+// Generic-kernel tile by the rows of an input block.  Blocks of more than 128
+// rows take 128-row tiles too: half the LDS of a 256-row tile, so twice the
+// workgroups per CU (measured: m4_n64_b8 FP32 127 -> 119 us, m3_n256_b16 on
+// the generic kernel 320 -> 262 us; STTSM_WIDE_MT=256 restores 256 rows).
 static TileCfg choose_tile(int Mblk)
 {
-    if (Mblk > 128) return {256, 64, 4, 1};
+    if (Mblk > 128) {
+        const char *e = getenv("STTSM_WIDE_MT");   // measurement override
+        if (e && atoi(e) == 256) return {256, 64, 4, 1};
+        return {128, 64, 2, 2};
+    }
     if (Mblk > 64) return {128, 64, 2, 2};
     if (Mblk > 32) return {64, 64, 2, 2};
     return {32, 128, 1, 4};
@@ -513,14 +521,20 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err, int cus)
         // Generic kernel, narrow row groups (few output columns, as in the
         // levels below the first and whenever p is small): 32-column tiles
         // when they cut the padded columns by a quarter or more.
-        if (!key.grouped && !S.fast && !S.fast_bf16 && S.tile.MT >= 128) {
+        if (!key.grouped && !S.fast && !S.fast_bf16 && Mblk > 64) {
             int64_t c32 = 0, c64 = 0;
             for (const GroupDesc &g : S.groups) {
                 const int64_t N = (int64_t)g.jcount * bC;
                 c32 += (N + 31) / 32 * 32;
                 c64 += (N + 63) / 64 * 64;
             }
-            if (4 * c32 <= 3 * c64) S.tile = TileCfg{S.tile.MT, 32, 4, 1};
+            if (4 * c32 <= 3 * c64) {
+                // 128 rows: half the LDS of a 256-row tile, so twice the
+                // workgroups per CU (m4_n64_b8 FP32 146 -> 125 us).
+                S.tile = TileCfg{128, 32, 4, 1};
+                const char *e = getenv("STTSM_NARROW_MT");   // measurement override: 256 rows
+                if (e && atoi(e) == 256 && Mblk > 128) S.tile.MT = 256;
+            }
         }
         if (S.fast) {
             // Tile of the block-copy kernel.  Below the first level a tile may
