@@ -18,6 +18,7 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16;
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 
 // fp32 -> bf16, round to nearest, ties to even (finite inputs).
 __device__ __forceinline__ u16 f2bf(float f)
@@ -536,6 +537,9 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
     f32x4 x_f32[X_PER_T];       // staged X (fp32 compute)
     u16x8 x_hi[X_PER_T], x_lo[X_PER_T];
 
+    // FP32 and split contractions always read fp32 input (the plan checks),
+    // so only the bf16 kernel carries the bf16-input load paths.
+    const bool in_f32 = CMP == CMP_BF16 ? a.in_f32 != 0 : true;
     const float *in32 = (const float *)a.in;
     const u16 *in16 = (const u16 *)a.in;
     const InEntry *row = a.in_tab + g.in_row;
@@ -582,14 +586,14 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
                 if (v < IN_VECS && s_mpart[0][mm] >= 0) {
                     const int64_t off = ioff + s_mpart[iq][mm] + (int64_t)(lk0 + kv * VK) * sk;
                     const bool whole = kfast && kv * VK + VK <= kvalid;
-                    if (whole && a.in_f32 && ((uintptr_t)(in32 + off) & 15) == 0) {
+                    if (whole && in_f32 && ((uintptr_t)(in32 + off) & 15) == 0) {
 #pragma unroll
                         for (int h = 0; h < VK / 4; ++h) {
                             const f32x4 w = *(const f32x4 *)(in32 + off + 4 * h);
 #pragma unroll
                             for (int e = 0; e < 4; ++e) in_f[t][4 * h + e] = w[e];
                         }
-                    } else if (VK == 8 && whole && !a.in_f32 && ((uintptr_t)(in16 + off) & 15) == 0) {
+                    } else if (VK == 8 && whole && !in_f32 && ((uintptr_t)(in16 + off) & 15) == 0) {
                         const u16x8 w = *(const u16x8 *)(in16 + off);
 #pragma unroll
                         for (int e = 0; e < VK; ++e) in_f[t][e] = bf2f(w[e & 7]);
@@ -598,7 +602,7 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
                         for (int e = 0; e < VK; ++e)
                             if (kv * VK + e < kvalid) {
                                 const int64_t o = off + (int64_t)e * sk;
-                                in_f[t][e] = a.in_f32 ? in32[o] : bf2f(in16[o]);
+                                in_f[t][e] = in_f32 ? in32[o] : bf2f(in16[o]);
                             }
                     }
                 }
@@ -633,14 +637,14 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
                     }
                     const int sk = sm.s_sqk[iq];
                     const int64_t off = ioff + s_mpart[iq][mm] + (int64_t)lk * sk;
-                    if (sk == 1 && a.in_f32 && ((uintptr_t)(in32 + off) & 15) == 0) {
+                    if (sk == 1 && in_f32 && ((uintptr_t)(in32 + off) & 15) == 0) {
 #pragma unroll
                         for (int h = 0; h < VK / 4; ++h) {
                             const f32x4 w = *(const f32x4 *)(in32 + off + 4 * h);
 #pragma unroll
                             for (int e = 0; e < 4; ++e) in_f[t][4 * h + e] = w[e];
                         }
-                    } else if (VK == 8 && sk == 1 && !a.in_f32 && ((uintptr_t)(in16 + off) & 15) == 0) {
+                    } else if (VK == 8 && sk == 1 && !in_f32 && ((uintptr_t)(in16 + off) & 15) == 0) {
                         const u16x8 w = *(const u16x8 *)(in16 + off);
 #pragma unroll
                         for (int e = 0; e < VK; ++e) in_f[t][e] = bf2f(w[e & 7]);
@@ -648,7 +652,60 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
 #pragma unroll
                         for (int e = 0; e < VK; ++e) {
                             const int64_t o = off + (int64_t)e * sk;
-                            in_f[t][e] = a.in_f32 ? in32[o] : bf2f(in16[o]);
+                            in_f[t][e] = in_f32 ? in32[o] : bf2f(in16[o]);
+                        }
+                    }
+                }
+            }
+        } else if (a.bA % 4 == 0) {
+            // Several whole blocks per chunk, bA a multiple of 4 but not of
+            // VK (bf16 chunks of b = 4 blocks): each group of 4 k values of
+            // a vector lies in one block and takes one table entry, and one
+            // 16- or 8-byte load where the contracted mode is stored
+            // fastest.  kvalid is a multiple of bA, so a group is either
+            // wholly valid or wholly past the end.
+#pragma unroll
+            for (int t = 0; t < IN_PER_T; ++t) {
+                const int v = tid + t * 256;
+                const int mm = v % MT, kv = v / MT;
+                in_mm[t] = mm;
+                in_kv[t] = kv;
+#pragma unroll
+                for (int e = 0; e < VK; ++e) in_f[t][e] = 0.f;
+                if (v < IN_VECS && s_mpart[0][mm] >= 0) {
+#pragma unroll
+                    for (int h = 0; h < VK / 4; ++h) {
+                        const int kk0 = kv * VK + 4 * h;
+                        if (kk0 < kvalid) {
+                            const int gi = kk0 / a.chunk_k;
+                            const int lk = lk0 + (kk0 - gi * a.chunk_k);
+                            int64_t ioff;
+                            int iq;
+                            if (tab_lds) {
+                                ioff = sm.s_ioff[blk0 + gi];
+                                iq = sm.s_iq[blk0 + gi];
+                            } else {
+                                const InEntry ie = row[blk0 + gi];
+                                ioff = ie.off;
+                                iq = ie.q;
+                            }
+                            const int sk = sm.s_sqk[iq];
+                            const int64_t off = ioff + s_mpart[iq][mm] + (int64_t)lk * sk;
+                            if (sk == 1 && in_f32 && ((uintptr_t)(in32 + off) & 15) == 0) {
+                                const f32x4 w = *(const f32x4 *)(in32 + off);
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) in_f[t][4 * h + e] = w[e];
+                            } else if (sk == 1 && !in_f32 && ((uintptr_t)(in16 + off) & 7) == 0) {
+                                const u16x4 w = *(const u16x4 *)(in16 + off);
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) in_f[t][4 * h + e] = bf2f(w[e]);
+                            } else {
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) {
+                                    const int64_t o = off + (int64_t)e * sk;
+                                    in_f[t][4 * h + e] = in_f32 ? in32[o] : bf2f(in16[o]);
+                                }
+                            }
                         }
                     }
                 }
@@ -680,7 +737,7 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
                                 iq = ie.q;
                             }
                             const int64_t off = ioff + s_mpart[iq][mm] + (int64_t)lk * sm.s_sqk[iq];
-                            in_f[t][e] = a.in_f32 ? in32[off] : bf2f(in16[off]);
+                            in_f[t][e] = in_f32 ? in32[off] : bf2f(in16[off]);
                         }
                     }
                 }
