@@ -259,7 +259,7 @@ def vectors_bench(args):
     import torch
     import paper_1301_7744_amd as st
     import synth
-    cfg = synth.CONFIGS[args.workload]
+    cfg = synth.workload(args.workload)
     m, n, b, V = cfg["m"], cfg["n"], cfg["bA"], args.vectors
     dev = torch.device("cuda:0")
     A_np, _ = synth.make_config_inputs(args.workload)
@@ -337,7 +337,7 @@ def rank_update_bench(args):
     import torch
     import paper_1301_7744_amd as st
     import synth
-    cfg = synth.CONFIGS[args.workload]
+    cfg = synth.workload(args.workload)
     m, n, p, bA, bC = cfg["m"], cfg["n"], cfg["p"], cfg["bA"], cfg["bC"]
     prec = st.PREC_NAMES[args.prec]
     dev = torch.device("cuda:0")
@@ -402,7 +402,7 @@ def rank_update_bench(args):
            "value": round(flops / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "bf16" if args.prec == "bf16" else "f32",
-           "data": "synthetic (seeded; symmetric A uniform[-1,1] mirrored from sorted-index entries, X N(0,1)/sqrt(n))",
+           "data": synth.workload_data(args.workload),
            "config": {"workload": args.workload + "_rows%d" % rows_list[0], "m": m, "n": n, "p": p, "bA": bA,
                       "bC": bC, "prec": args.prec, "rows_per_pass": rows_list[0], "launch": "graph replay"},
            "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
@@ -446,7 +446,7 @@ def main():
     import paper_1301_7744_amd as st
     import synth
 
-    cfg = synth.CONFIGS[args.workload]
+    cfg = synth.workload(args.workload)
     m, n, p, bA, bC = cfg["m"], cfg["n"], cfg["p"], cfg["bA"], cfg["bC"]
     prec = st.PREC_NAMES[args.prec]
     dev = torch.device("cuda:0")
@@ -578,7 +578,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "bf16": "bf16", "bf16x3_fp32": "bf16x3+f32", "bf16x3_bf16": "bf16x3+bf16"}[args.prec],
-        "data": "synthetic (seeded; symmetric A uniform[-1,1] mirrored from sorted-index entries, X N(0,1)/sqrt(n))",
+        "data": synth.workload_data(args.workload),
         "config": {"workload": args.workload, "m": m, "n": n, "p": p, "bA": bA, "bC": bC, "prec": args.prec,
                    "flops_per_step": flops, "mfma_roofline_frac": round(gflops / (peak * 1e3), 4),
                    "launch": "graph replay" if graph is not None else "eager",

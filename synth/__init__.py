@@ -156,8 +156,37 @@ def rect_cases():
     return out
 
 
+def rect_inputs(case):
+    """(A, X, lams, vecs) of a rank-r rectangular case: A = sum_i lam_i
+    a_i^{o m} rounded to float32, X with seed case seed + 1000."""
+    lams, vecs = rank_r_factors(case["n"], case["rank"], case["seed"])
+    A = rank_r_symmetric(case["m"], lams, vecs).astype(np.float32)
+    X = change_of_basis(case["p"], case["n"], case["seed"] + 1000)
+    return A, X, lams, vecs
+
+
+def workload(name: str) -> dict:
+    """Shape of a named workload: a CONFIGS entry or a rect_cases() name."""
+    if name in CONFIGS:
+        return CONFIGS[name]
+    for c in rect_cases():
+        if c["name"] == name:
+            return c
+    raise KeyError("unknown workload %r" % name)
+
+
+def workload_data(name: str) -> str:
+    """How a named workload's inputs are drawn (for reports)."""
+    if name in CONFIGS:
+        return "synthetic (seeded; symmetric A uniform[-1,1] mirrored from sorted-index entries, X N(0,1)/sqrt(n))"
+    return "synthetic (seeded; rank-8 symmetric A = sum lam_i a_i^{o4}, a_i N(0,I)/sqrt(n), lam_i U[0.5,2]; X N(0,1)/sqrt(n))"
+
+
 def make_config_inputs(name: str):
     """(A, X) float32 dense inputs for a named workload."""
+    if name not in CONFIGS:
+        A, X, _, _ = rect_inputs(workload(name))
+        return A, X
     c = CONFIGS[name]
     A = symmetric_uniform(c["m"], c["n"], c["seed_a"])
     X = change_of_basis(c["p"], c["n"], c["seed_x"], scale=c.get("x_scale"))

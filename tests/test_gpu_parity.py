@@ -262,10 +262,8 @@ def _rect_inputs(case):
     (n, seed): shared by the block-size and precision variants."""
     key = (case["m"], case["n"], case["p"], case["rank"], case["seed"])
     if key not in _RECT:
-        m, n, p = case["m"], case["n"], case["p"]
-        lams, vecs = synth.rank_r_factors(n, case["rank"], case["seed"])
-        A = synth.rank_r_symmetric(m, lams, vecs).astype(np.float32)
-        X = synth.change_of_basis(p, n, case["seed"] + 1000)
+        m = case["m"]
+        A, X, lams, vecs = synth.rect_inputs(case)
         Cref = oracle.chain(A.astype(np.float64), X.astype(np.float64))
         Cclosed = closed_forms.rank_r(lams, vecs, X.astype(np.float64), m)
 
