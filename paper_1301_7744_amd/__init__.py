@@ -337,7 +337,7 @@ def sttsm_rank_update_workspace_bytes(m: int, n: int, p: int, bA: int, bC: int, 
     return wsb
 
 
-def sttsm_rank_update(A_bcss, X, m: int, n: int, p: int, bA: int, bC: int, prec: int = PREC_FP32, rows: int = 1,
+def sttsm_rank_update(A_bcss, X, m: int, n: int, p: int, bA: int, bC: int, prec: int = PREC_FP32, rows: int = 8,
                       C=None, ws=None, stream=None):
     """C := [A; X, ..., X] by the rank-update form: passes of `rows` block
     rows of A x_1 X ... x_{m-1} X, each added to C as a rank update.

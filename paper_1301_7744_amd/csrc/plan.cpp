@@ -904,6 +904,10 @@ bool rank_plan_build_host(const Plan &P, int rows, RankPlan *R, std::string *err
             if (i0 < a0 || i0 >= a0 + Sc) continue;
             GroupDesc g = L.groups[gi];
             const int64_t jr = (g.out_base / blk - i0) / nbar;
+            if ((jr * nbar + i0) * blk != g.out_base || g.out_jstride != (int64_t)nbar * blk) {
+                *err = "rank-update form: unexpected layout of T^(1)";
+                return false;
+            }
             g.out_base = (jr * Sc + (i0 - a0)) * blk;
             g.out_jstride = (int64_t)Sc * blk;
             remap[gi] = (int32_t)row.groups.size();
@@ -935,6 +939,10 @@ bool rank_plan_build_host(const Plan &P, int rows, RankPlan *R, std::string *err
             for (int ib = a0; ib < a0 + Sc; ++ib) {
                 InEntry e = U.in_tab[(size_t)g0.in_row + ib];
                 const int64_t jr = (e.off / blk - ib) / nbar;
+                if ((jr * nbar + ib) * blk != e.off || e.q != 0) {
+                    *err = "rank-update form: unexpected layout of T^(1)";
+                    return false;
+                }
                 e.off = (jr * Sc + (ib - a0)) * blk;
                 upd.in_tab.push_back(e);
             }
