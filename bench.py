@@ -33,11 +33,12 @@ def measured_traffic(workload, prec, level):
     changed since it was taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, prec))
-    src = os.path.join(ROOT, "paper_1301_7744_amd", "csrc", "kernels.hip")
+    src_name = "stage_bf16.hip" if prec == "bf16" else "kernels.hip"   # the file holding the level kernels
+    src = os.path.join(ROOT, "paper_1301_7744_amd", "csrc", src_name)
     try:
         d = json.load(open(path))
         cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if d.get("kernels_hip_sha256") != cur:
+        if d.get("source", "kernels.hip") != src_name or d.get("source_sha256", d.get("kernels_hip_sha256")) != cur:
             return None
         e = d["per_level"][str(level)]
         return int(e["fetch_bytes"] + e["write_bytes"])
