@@ -16,6 +16,9 @@ Components
   chain       (O2)  successive dense mode products (§5.2, Figure 1 bottom right)
   rank_update       the rank-update form of §8 (C as a sum of rank-b updates)
   entry       (O3)  one output entry by the literal sum
+  entries     (O3)  many entries by the literal sum, each with its
+                    root-sum-square of terms (the rounding-error scale)
+  term_rss          that root-sum-square for every entry (O2 on A*A, X*X)
   closed_forms (O4) m=2 matrix identity, rank-1 / rank-r forms
   bcss_ref          independent BCSS enumerator, pack and unpack
   costs             storage / work counts by enumeration and by the paper's formulas
@@ -39,7 +42,7 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O3", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
-               "-fPIC", "-shared", "-std=c11", "-o", tmp, _SRC]
+               "-fPIC", "-shared", "-std=c11", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -54,12 +57,14 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         i64p = ctypes.POINTER(ctypes.c_int64)
         lib.oracle_entry.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, dp, i64p, dp]
+        lib.oracle_entries.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, dp, ctypes.c_int64,
+                                       i64p, dp, dp]
         lib.oracle_direct_sum.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, dp, dp]
         lib.oracle_mode_product.argtypes = [ctypes.c_int, i64p, dp, ctypes.c_int, dp, ctypes.c_int64, dp]
         lib.oracle_chain.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, dp, dp,
                                      ctypes.POINTER(dp)]
         lib.oracle_num_threads.argtypes = []
-        for f in (lib.oracle_entry, lib.oracle_direct_sum, lib.oracle_mode_product,
+        for f in (lib.oracle_entry, lib.oracle_entries, lib.oracle_direct_sum, lib.oracle_mode_product,
                   lib.oracle_chain, lib.oracle_num_threads):
             f.restype = ctypes.c_int
         _lib = lib
@@ -100,6 +105,33 @@ def entry(A: np.ndarray, X: np.ndarray, j) -> float:
     if rc:
         raise ValueError("oracle_entry rejected its arguments")
     return out.value
+
+
+def entries(A: np.ndarray, X: np.ndarray, js):
+    """O3 for many output tuples (js: (count, m) integers): each entry by the
+    literal n^m-term sum of §2.5, and the root-sum-square of the same terms,
+    sqrt(sum_i t_i^2), the scale against which an entry's rounding error is
+    measured.  Returns (sums, rss), float64 arrays of length count."""
+    m, n, p = _check(A, X)
+    A64, X64 = _as_dense_f64(A), np.ascontiguousarray(X, dtype=np.float64)
+    J = np.ascontiguousarray(js, dtype=np.int64).reshape(-1, m)
+    sums = np.zeros(J.shape[0])
+    rss = np.zeros(J.shape[0])
+    rc = _load().oracle_entries(m, n, p, _dptr(A64), _dptr(X64), J.shape[0],
+                                J.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dptr(sums), _dptr(rss))
+    if rc:
+        raise ValueError("oracle_entries rejected its arguments")
+    return sums, rss
+
+
+def term_rss(A: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """For every output entry j, sqrt(sum_i t_i^2) over the n^m terms
+    t_i = alpha_i chi_{j_0 i_0} ... chi_{j_{m-1} i_{m-1}} of §2.5: the
+    squared terms are the terms of the same operation on the entrywise
+    squares of A and X, so this is the O2 chain on (A*A, X*X), then a square
+    root.  Dense, FP64, Fortran order, extent p in every mode."""
+    A64, X64 = _as_dense_f64(A), np.asarray(X, dtype=np.float64)
+    return np.sqrt(chain(A64 * A64, X64 * X64))
 
 
 def direct_sum(A: np.ndarray, X: np.ndarray) -> np.ndarray:

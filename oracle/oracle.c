@@ -16,12 +16,15 @@
  *
  * Functions:
  *   oracle_entry       one output entry by the literal n^m-term sum  (O3)
+ *   oracle_entries     many entries by that sum, with each entry's
+ *                      root-sum-square of terms (its rounding-error scale)
  *   oracle_direct_sum  every output entry by that literal sum        (O1)
  *   oracle_mode_product / oracle_chain  successive dense mode products (O2)
  */
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <math.h>
 
 #define ORACLE_MAX_ORDER 8
 
@@ -59,6 +62,52 @@ int oracle_entry(int m, int64_t n, int64_t p, const double *A, const double *X,
         }
     }
     *out = gamma;
+    return 0;
+}
+
+/*
+ * O3 over a list of entries, with each entry's error scale.  For each of the
+ * `count` output tuples j (m indices each, J[e*m + k]) this evaluates, by the
+ * same literal n^m-term sum as oracle_entry (§2.5), both
+ *   sums[e] = sum_i  t_i,          t_i = alpha_i chi_{j_0 i_0} ... chi_{j_{m-1} i_{m-1}},
+ *   rss[e]  = sqrt(sum_i t_i^2),
+ * the root-sum-square of the same terms.  rss is the scale of the rounding
+ * error of any summation of the terms in which each rounding is independent
+ * and relative: it is what an entry-by-entry tolerance is measured against.
+ * Entries run in parallel; each one's sums run in the fixed odometer order of
+ * oracle_entry (i_0 fastest).  Returns 0, or -1 on bad arguments.
+ */
+int oracle_entries(int m, int64_t n, int64_t p, const double *A, const double *X,
+                   int64_t count, const int64_t *J, double *sums, double *rss)
+{
+    if (m < 1 || m > ORACLE_MAX_ORDER || n < 1 || p < 1 || count < 0 || !A || !X ||
+        (count > 0 && (!J || !sums || !rss)))
+        return -1;
+    for (int64_t e = 0; e < count; ++e)
+        for (int k = 0; k < m; ++k)
+            if (J[e * m + k] < 0 || J[e * m + k] >= p) return -1;
+    int64_t total = 1;
+    for (int k = 0; k < m; ++k) total *= n;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t e = 0; e < count; ++e) {
+        const int64_t *j = J + e * m;
+        int64_t i[ORACLE_MAX_ORDER];
+        for (int k = 0; k < m; ++k) i[k] = 0;
+        double gamma = 0.0, sq = 0.0;
+        for (int64_t flat = 0; flat < total; ++flat) {
+            double term = A[flat];
+            for (int k = 0; k < m; ++k)
+                term *= X[j[k] * n + i[k]];
+            gamma += term;
+            sq += term * term;
+            for (int k = 0; k < m; ++k) {
+                if (++i[k] < n) break;
+                i[k] = 0;
+            }
+        }
+        sums[e] = gamma;
+        rss[e] = sqrt(sq);
+    }
     return 0;
 }
 

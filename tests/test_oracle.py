@@ -61,6 +61,79 @@ def test_entry_matches_chain_at_full_size():
         assert abs(oracle.entry(A, X, j) - C[tuple(j)]) <= 1e-12 * np.abs(C).max()
 
 
+def _python_terms(A, X, j):
+    """Every term alpha_i chi_{j_0 i_0} ... chi_{j_{m-1} i_{m-1}} of one
+    output entry (§2.5), by plain Python loops over itertools.product."""
+    m, n = A.ndim, A.shape[0]
+    out = []
+    for i in itertools.product(range(n), repeat=m):
+        t = float(A[i])
+        for k in range(m):
+            t *= float(X[j[k], i[k]])
+        out.append(t)
+    return out
+
+
+@pytest.mark.parametrize("m,n,p", [(1, 3, 2), (2, 3, 4), (3, 3, 2), (3, 2, 3), (4, 2, 2)])
+def test_direct_sum_matches_python_loops(m, n, p):
+    """O1 against a brute-force Python evaluation of the defining sum, on a
+    non-symmetric A (so a swapped index would show)."""
+    A = nonsym((n,) * m, (m, n, p, 41))
+    X = synth.rng((m, n, p, 42)).standard_normal((p, n))
+    C = oracle.direct_sum(A, X)
+    for j in itertools.product(range(p), repeat=m):
+        assert abs(C[j] - math.fsum(_python_terms(A, X, j))) <= 1e-13 * max(1.0, abs(C[j]))
+
+
+def test_entries_match_direct_sum_config1():
+    """O3 (per-entry literal sums, in parallel) against O1 on every one of
+    the 4096 entries of m=3, n=p=16."""
+    A, X = synth.make_config_inputs("m3_n16_b4")
+    A, X = A.astype(np.float64), X.astype(np.float64)
+    C = oracle.direct_sum(A, X)
+    js = np.array(list(itertools.product(range(16), repeat=3)))
+    sums, _ = oracle.entries(A, X, js)
+    assert np.array_equal(sums, C[tuple(js.T)])
+
+
+@pytest.mark.parametrize("m,n,p", [(1, 4, 3), (2, 3, 4), (3, 3, 2), (4, 2, 3)])
+def test_term_rss_matches_python_loops(m, n, p):
+    """The rounding-error scale sqrt(sum_i t_i^2) of every entry, from the
+    chain on squares and from the literal per-entry loop, against Python."""
+    A = nonsym((n,) * m, (m, n, p, 43))
+    X = synth.rng((m, n, p, 44)).standard_normal((p, n))
+    R = oracle.term_rss(A, X)
+    js = np.array(list(itertools.product(range(p), repeat=m)))
+    _, rss = oracle.entries(A, X, js)
+    for e, j in enumerate(js):
+        want = math.sqrt(math.fsum(t * t for t in _python_terms(A, X, tuple(j))))
+        assert abs(R[tuple(j)] - want) <= 1e-13 * want
+        assert abs(rss[e] - want) <= 1e-13 * want
+
+
+@pytest.mark.parametrize("m,n,p", [(2, 7, 5), (3, 6, 4), (4, 5, 3)])
+def test_term_rss_rank1_closed_form(m, n, p):
+    """A = a o ... o a: the terms of entry j factor over the modes, so
+    sum_i t_i^2 = prod_k (X^2 a^2)_{j_k}, i.e. rss = (|X|^2 a^2)^{1/2} taken
+    as an outer power."""
+    a = synth.rng((m, n, 45)).standard_normal(n)
+    A = closed_forms.outer_power(a, m)
+    X = synth.change_of_basis(p, n, (m, 46)).astype(np.float64)
+    want = closed_forms.outer_power(np.sqrt((X * X) @ (a * a)), m)
+    assert rel(oracle.term_rss(A, X), want) <= 1e-13
+
+
+@pytest.mark.parametrize("m,n,p", [(2, 9, 6), (3, 7, 5), (4, 5, 4)])
+def test_term_rss_bounds(m, n, p):
+    """Cauchy-Schwarz over the n^m terms: |C_j| <= sqrt(n^m) rss_j, and
+    rss_j <= sum_i |t_i| = [|A|; |X|, ..., |X|]_j."""
+    A = sym(m, n, (m, 47))
+    X = synth.change_of_basis(p, n, (m, 48)).astype(np.float64)
+    R = oracle.term_rss(A, X)
+    assert np.all(np.abs(oracle.chain(A, X)) <= np.sqrt(float(n) ** m) * R * (1 + 1e-13))
+    assert np.all(R <= oracle.chain(np.abs(A), np.abs(X)) * (1 + 1e-13))
+
+
 # ------------------------------------------------------- textbook identities
 @pytest.mark.parametrize("n,p", [(1, 1), (4, 3), (17, 9), (40, 40)])
 def test_matrix_case_is_XAXt(n, p):
