@@ -134,6 +134,72 @@ def term_rss(A: np.ndarray, X: np.ndarray) -> np.ndarray:
     return np.sqrt(chain(A64 * A64, X64 * X64))
 
 
+def error_scale(A: np.ndarray, X: np.ndarray, last_mode: int = 0, temps=None) -> np.ndarray:
+    """Per-entry rounding-error scale of the chain of mode products (§5.2,
+    §6), for a symmetric A.
+
+    The chain runs modes m-1, m-2, ..., last_mode (last_mode = 0 is sttsm,
+    last_mode = 1 the product in every mode but mode 0 of §2.5).  Its
+    operands are the entries of A, the entries of every temporary
+    T^(k) = A x_(m-1) X ... x_k X (k = last_mode+1 .. m-1) and the entries of
+    X used in each contracted mode.  A relative change delta of one operand
+    entry e changes output entry j by delta * e * d(out_j)/de to first order.
+    This returns, for every output entry j,
+
+        S_j = sqrt( sum over every operand entry e of (e * d(out_j)/de)^2 ),
+
+    the 2-norm of those sensitivities, computed as sums of squared terms:
+      * A entries:   (A*A) x_(m-1) (X*X) ... x_last (X*X)  (the terms of the
+        same operation on entrywise squares);
+      * T^(k) entries: (T^(k)*T^(k)) x_(k-1) (X*X) ... x_last (X*X);
+      * X entries in mode l: the sensitivity to chi_(j_l, i) is the output
+        with mode l left uncontracted, which for symmetric A is T^(last+1)
+        with its free mode `last` moved to l (Theorem 1 and the symmetry of
+        A), so this part is (T^(last+1)^2 x_last (X*X)) with mode `last`
+        moved to l, summed over l = last..m-1 (T^(m) meaning A).
+    An independent relative rounding of every operand entry by at most u
+    then gives an error of about u * S_j / sqrt(3) in entry j (sharing of one
+    rounded value between mirrored positions raises this by at most the
+    square root of the number of positions that share it).
+
+    Dense, FP64, Fortran order, the shape of the chain's output.  `temps`
+    may pass the {k: T^(k)} of chain(A, X, keep_temps=True) to skip
+    recomputing them."""
+    A = _as_dense_f64(A)
+    X = np.asarray(X, dtype=np.float64)
+    m, n, p = _check(A, X)
+    s = int(last_mode)
+    if s < 0 or s >= m:
+        raise ValueError("last_mode must be in 0..m-1")
+    if m == 2 and s == 0:
+        # The same three parts by library matrix products (§3.1: the m = 2
+        # chain is T^(1) = A X^T, C = X T^(1)); X2 A2 X2^T is the A part,
+        # X2 (T^(1))^2 the T^(1) part and the mode-0 X part, its transpose
+        # the mode-1 X part.
+        X2 = X * X
+        T1 = A @ X.T
+        Q = X2 @ (T1 * T1)
+        return np.asfortranarray(np.sqrt(X2 @ (A * A) @ X2.T + 2.0 * Q + Q.T))
+    if temps is None and s + 1 < m:
+        _, temps = chain(A, X, keep_temps=True)
+    X2 = X * X
+
+    def contract(T, hi):
+        for k in range(hi, s - 1, -1):
+            T = mode_product(T, k, X2)
+        return T
+
+    S2 = contract(A * A, m - 1)
+    for k in range(s + 1, m):
+        S2 += contract(temps[k] * temps[k], k - 1)
+    W = temps[s + 1] if s + 1 < m else A
+    Q = mode_product(W * W, s, X2)
+    del W
+    for l in range(s, m):
+        S2 += np.moveaxis(Q, s, l)
+    return np.sqrt(S2)
+
+
 def direct_sum(A: np.ndarray, X: np.ndarray) -> np.ndarray:
     """O1: every entry of C by the literal sum of §2.5; cost (m+1) n^m p^m."""
     m, n, p = _check(A, X)

@@ -3,19 +3,21 @@ the same seeded inputs.
 
 Integer/byte work (pack, unpack, padding) is compared bit for bit; floating
 point results by relative Frobenius error over the dense C with the bounds in
-gpu_util (FP32 1e-5; BF16 sqrt(2m) 2^-8; split-BF16x3 2e-5)."""
+gpu_util (FP32 1e-5; BF16 sqrt(2m) 2^-8; split-BF16x3 2e-5) and, entry by
+entry, by |C_gpu - C_ref| <= TAU u S_j with S_j the oracle's per-entry error
+scale and u the precision form's unit roundoff (gpu_util.check_entries).  At
+every full-size workload 256 output entries are also evaluated by the
+literal n^m-term sum of Eq. (cob) (O3) and checked the same way."""
 import numpy as np
 import pytest
 
 import oracle
 from oracle import bcss_ref, closed_forms
 import synth
-from gpu_util import (TOL_FP32, TOL_X3_FIRST_FP32, TOL_X3_STAGE0, dev_dense, err, padding_mask, ref_bcss,
-                      run, say, tol_bf16)
+from gpu_util import (P32, PBF, PX3B, PX3F, TOL_FP32, TOL_X3_FIRST_FP32, TOL_X3_STAGE0, check_entries,
+                      check_literal_entries, dev_dense, err, padding_mask, ref_bcss, reference, run, say, tol_bf16)
 
 pytestmark = pytest.mark.gpu
-
-P32, PBF, PX3F, PX3B = 0, 1, 2, 3
 
 
 def st():
@@ -95,10 +97,11 @@ def test_fp32_small_vs_oracle(m, n, p, bA, bC):
     A = synth.symmetric_uniform(m, n, (m, n, p, 11))
     X = synth.change_of_basis(p, n, (m, n, p, 12))
     got = run(A, X, bA, bC, P32)
-    ref = ref_bcss(A.astype(np.float64), X.astype(np.float64), bC)
+    ref, S = reference(A, X, bC)
     e = err(got, ref, m, p, bC)
     say("  rel err", e)
     assert e <= TOL_FP32
+    check_entries(got, ref, S, P32, -(-n // bA) * bA)
     mask = padding_mask(m, p, bC)
     assert np.all(got[mask] == 0.0)
 
@@ -111,29 +114,21 @@ def test_fp32_config1_vs_direct_sum():
     e = err(got, ref, 3, 16, 4)
     say("config1 fp32 rel err", e)
     assert e <= TOL_FP32
+    _, S = reference(A, X, 4)
+    check_entries(got, ref, S, P32, 16)
 
 
 def test_fp32_config2_full():
-    """m=3, n=p=256, b=16 (the measured workload): full C against O2 and
-    64 sampled entries against the literal per-entry sum (O3)."""
+    """m=3, n=p=256, b=16 (the measured workload): full C against O2, entry
+    by entry, and 256 sampled entries against the literal per-entry sum (O3)."""
     A, X = synth.make_config_inputs("m3_n256_b16")
     got = run(A, X, 16, 16, P32)
-    A64, X64 = A.astype(np.float64), X.astype(np.float64)
-    Cd = oracle.chain(A64, X64)
-    e = err(got, bcss_ref.pack(Cd, 16), 3, 256, 16)
+    ref, S = reference(A, X, 16)
+    e = err(got, ref, 3, 256, 16)
     say("config2 fp32 rel err", e)
     assert e <= TOL_FP32
-    index = bcss_ref.block_index(3, 16)
-    g = synth.rng(7)
-    scale = np.abs(Cd).max()
-    for _ in range(64):
-        j = np.sort(g.integers(0, 256, size=3))[g.permutation(3)]
-        lit = oracle.entry(A64, X64, j)
-        u = sorted(range(3), key=lambda i: j[i] // 16)
-        blk = tuple(int(j[i] // 16) for i in u)
-        loc = [int(j[i] % 16) for i in u]
-        gpu = got[index[blk], loc[0] + 16 * loc[1] + 256 * loc[2]]
-        assert abs(gpu - lit) <= 1e-5 * scale
+    check_entries(got, ref, S, P32, 256)
+    check_literal_entries({P32: got}, A, X, 16, ref, S, 256)
 
 
 def test_temporaries_match_oracle():
@@ -180,11 +175,12 @@ def test_reduced_precision_small(prec, case):
     A = synth.symmetric_uniform(m, n, (m, n, 31))
     X = synth.change_of_basis(p, n, (m, n, 32))
     got = run(A, X, bA, bC, prec)
-    ref = ref_bcss(A.astype(np.float64), X.astype(np.float64), bC)
+    ref, S = reference(A, X, bC)
     e = err(got, ref, m, p, bC)
     bound = {PBF: tol_bf16(m), PX3F: TOL_X3_FIRST_FP32, PX3B: tol_bf16(m)}[prec]
     say("  rel err", e, "bound", bound)
     assert e <= bound
+    check_entries(got, ref, S, prec, -(-n // bA) * bA)
     assert np.all(got[padding_mask(m, p, bC)] == 0.0)
 
 
@@ -195,9 +191,11 @@ def test_bf16_inputs():
     A = synth.round_to_bf16(synth.symmetric_uniform(m, n, 41))
     X = synth.round_to_bf16(synth.change_of_basis(p, n, 42))
     got = run(A, X, b, b, PBF, dtype=torch.bfloat16)
-    e = err(got, ref_bcss(A.astype(np.float64), X.astype(np.float64), b), m, p, b)
+    ref, S = reference(A, X, b)
+    e = err(got, ref, m, p, b)
     say("bf16-input rel err", e)
     assert e <= tol_bf16(m)
+    check_entries(got, ref, S, PBF, n)
 
 
 def test_split_stage0_recovers_fp32():
@@ -206,22 +204,27 @@ def test_split_stage0_recovers_fp32():
     m, n, p, b = 3, 64, 64, 16
     A = synth.symmetric_uniform(m, n, 51)
     X = synth.change_of_basis(p, n, 52)
-    _, temps = oracle.chain(A.astype(np.float64), X.astype(np.float64), keep_temps=True)
+    A64, X64 = A.astype(np.float64), X.astype(np.float64)
+    _, temps = oracle.chain(A64, X64, keep_temps=True)
     ref = temps[m - 1]
+    scale = oracle.error_scale(A64, X64, last_mode=m - 1)     # the first level alone
     errs = {}
     for prec in (PX3F, PBF):
         _, ws = run(A, X, b, b, prec, keep_ws=True)
         T = st().temporary(ws, m, n, p, b, b, prec, m - 1).double().cpu().numpy()
         nbar = n // b
         pf = bcss_ref.sorted_block_tuples(m - 1, nbar)
-        num = den = 0.0
+        got_l, ref_l, sc_l = [], [], []
         for jb in range(p // b):
             for q, s in enumerate(pf):
                 sl = tuple(slice(si * b, (si + 1) * b) for si in s) + (slice(jb * b, (jb + 1) * b),)
-                r = ref[sl].ravel(order="F")
-                num += float(np.sum((T[jb, q] - r) ** 2))
-                den += float(np.sum(r ** 2))
-        errs[prec] = (num / den) ** 0.5
+                got_l.append(T[jb, q])
+                ref_l.append(ref[sl].ravel(order="F"))
+                sc_l.append(scale[sl].ravel(order="F"))
+        got_a, ref_a = np.array(got_l), np.array(ref_l)
+        errs[prec] = float(np.linalg.norm(got_a - ref_a) / np.linalg.norm(ref_a))
+        if prec == PX3F:
+            check_entries(got_a, ref_a, np.array(sc_l), PX3F, n, what="T^(m-1)")
     say("T^(m-1) errors", errs)
     assert errs[PX3F] <= TOL_X3_STAGE0
     assert errs[PBF] > 10 * errs[PX3F]
@@ -236,38 +239,48 @@ def sweep_refs():
     return {}
 
 
-@pytest.mark.parametrize("prec", [P32, PBF, PX3F])
+@pytest.mark.parametrize("prec", [P32, PBF, PX3F, PX3B])
 @pytest.mark.parametrize("name", SWEEP)
 def test_order_sweep_full(name, prec, sweep_refs):
+    """Each order-sweep workload in every precision form: the whole C by
+    relative Frobenius error and entry by entry, and 256 entries against the
+    literal sum (O3)."""
     c = synth.CONFIGS[name]
     m, n, p, b = c["m"], c["n"], c["p"], c["bA"]
     say("sweep", name, prec)
     A, X = synth.make_config_inputs(name)
-    if name not in sweep_refs:
-        A64, X64 = A.astype(np.float64), X.astype(np.float64)
-        Cd = closed_forms.matrix_case(A64, X64) if m == 2 else oracle.chain(A64, X64)
-        sweep_refs[name] = bcss_ref.pack(np.asfortranarray(Cd), b)
+    if sweep_refs.get("name") != name:
+        sweep_refs.clear()
+        sweep_refs["name"] = name
+        sweep_refs["ref"], sweep_refs["S"] = reference(A, X, b)
+    ref, S = sweep_refs["ref"], sweep_refs["S"]
     got = run(A, X, b, b, prec)
-    e = err(got, sweep_refs[name], m, p, b)
-    bound = {P32: TOL_FP32, PBF: tol_bf16(m), PX3F: TOL_X3_FIRST_FP32}[prec]
+    e = err(got, ref, m, p, b)
+    bound = {P32: TOL_FP32, PBF: tol_bf16(m), PX3F: TOL_X3_FIRST_FP32, PX3B: tol_bf16(m)}[prec]
     say("  rel err", e, "bound", bound)
     assert e <= bound
+    check_entries(got, ref, S, prec, n)
+    check_literal_entries({prec: got}, A, X, b, ref, S, n, cache=sweep_refs)
 
 
 _RECT = {}
 
 
 def _rect_inputs(case):
-    """A (fp32), X, the oracle's C on those values and the closed form, per
-    (n, seed): shared by the block-size and precision variants."""
+    """A (fp32), X, the oracle's C on those values, its per-entry error scale
+    and the closed form, per (n, seed): shared by the block-size and
+    precision variants (and so are the O3 literal sums, in the cache)."""
     key = (case["m"], case["n"], case["p"], case["rank"], case["seed"])
     if key not in _RECT:
+        _RECT.clear()
         m = case["m"]
         A, X, lams, vecs = synth.rect_inputs(case)
-        Cref = oracle.chain(A.astype(np.float64), X.astype(np.float64))
-        Cclosed = closed_forms.rank_r(lams, vecs, X.astype(np.float64), m)
-
-        _RECT[key] = (A, X, Cref, Cclosed)
+        A64, X64 = A.astype(np.float64), X.astype(np.float64)
+        Cref, temps = oracle.chain(A64, X64, keep_temps=True)
+        S = oracle.error_scale(A64, X64, temps=temps)
+        del temps, A64
+        Cclosed = closed_forms.rank_r(lams, vecs, X64, m)
+        _RECT[key] = (A, X, Cref, Cclosed, S, {})
     return _RECT[key]
 
 
@@ -277,16 +290,19 @@ def test_rank8_rectangular(case, prec):
     """m=4, p=32, rank-8 A: against the closed form sum lam (X a)^{o4}."""
     m, n, p, bA, bC = case["m"], case["n"], case["p"], case["bA"], case["bC"]
     say("rect", case["name"], prec)
-    A, X, Cref, Cclosed = _rect_inputs(case)
+    A, X, Cref, Cclosed, S, cache = _rect_inputs(case)
     got = run(A, X, bA, bC, prec)
     # the GPU sees A rounded to fp32: compare with the exact result for those values
-    ref = bcss_ref.pack(Cref, bC)
+    ref, Sb = bcss_ref.pack(Cref, bC), bcss_ref.pack(S, bC)
     e = err(got, ref, m, p, bC)
     closed = bcss_ref.pack(Cclosed, bC)
     e_closed = err(got, closed, m, p, bC)
     bound = TOL_FP32 if prec == P32 else tol_bf16(m)
     say("  rel err", e, "vs closed form", e_closed)
     assert e <= bound and e_closed <= bound
+    kpad = -(-n // bA) * bA
+    check_entries(got, ref, Sb, prec, kpad)
+    check_literal_entries({prec: got}, A, X, bC, ref, Sb, kpad, cache=cache)
     assert np.all(got[padding_mask(m, p, bC)] == 0.0)
 
 
@@ -424,9 +440,11 @@ def test_bf16_block_copy_and_generic_kernels(m, n, p, b, generic, monkeypatch):
     A = synth.round_to_bf16(synth.symmetric_uniform(m, n, (m, n, p, 93)))
     X = synth.round_to_bf16(synth.change_of_basis(p, n, (m, n, p, 94)))
     got = run(A, X, b, b, PBF, dtype=torch.bfloat16)
-    e = err(got, ref_bcss(A.astype(np.float64), X.astype(np.float64), b), m, p, b)
+    ref, S = reference(A, X, b)
+    e = err(got, ref, m, p, b)
     say("  rel err", e, "bound", tol_bf16(m))
     assert e <= tol_bf16(m)
+    check_entries(got, ref, S, PBF, -(-n // b) * b)
     assert np.all(got[padding_mask(m, p, b)] == 0.0)
 
 
@@ -448,24 +466,30 @@ def test_bf16_tile_variants(tiles, m, n, p, b, monkeypatch):
     A = synth.round_to_bf16(synth.symmetric_uniform(m, n, (m, n, p, 95)))
     X = synth.round_to_bf16(synth.change_of_basis(p, n, (m, n, p, 96)))
     got = run(A, X, b, b, PBF, dtype=torch.bfloat16)
-    e = err(got, ref_bcss(A.astype(np.float64), X.astype(np.float64), b), m, p, b)
+    ref, S = reference(A, X, b)
+    e = err(got, ref, m, p, b)
     say("  rel err", e, "bound", tol_bf16(m))
     assert e <= tol_bf16(m)
+    check_entries(got, ref, S, PBF, -(-n // b) * b)
     assert np.all(got[padding_mask(m, p, b)] == 0.0)
 
 
 def test_bf16_block_copy_config2_full():
     """m = 3, n = p = 256, b = 16 in bf16 through the block-copy kernel (the
     bench workload at bf16): the whole C against the oracle chain on the same
-    bf16 values."""
+    bf16 values, by Frobenius error and entry by entry, and 256 entries
+    against the literal sum (O3)."""
     import torch
     m, n, p, b = 3, 256, 256, 16
     A, X = synth.make_config_inputs("m3_n256_b16")
     A, X = synth.round_to_bf16(A), synth.round_to_bf16(X)
     got = run(A, X, b, b, PBF, dtype=torch.bfloat16)
-    e = err(got, ref_bcss(A.astype(np.float64), X.astype(np.float64), b), m, p, b)
+    ref, S = reference(A, X, b)
+    e = err(got, ref, m, p, b)
     say("config m3_n256_b16 bf16 rel err", e, "bound", tol_bf16(m))
     assert e <= tol_bf16(m)
+    check_entries(got, ref, S, PBF, n)
+    check_literal_entries({PBF: got}, A, X, b, ref, S, n)
 
 
 # ------------------------------------------------------------------ all modes but one
@@ -502,12 +526,15 @@ def test_all_but_one_vs_oracle(case):
     T, _ = st().sttsm_all_but_one(Ab, Xd, m, n, p, bA, bC, prec)
     torch.cuda.synchronize()
     got = T.double().cpu().numpy()
-    ref = _blocks_of_T1(oracle.all_but_one(A.astype(np.float64), X.astype(np.float64)), m, n, p, bA, bC)
+    A64, X64 = A.astype(np.float64), X.astype(np.float64)
+    ref = _blocks_of_T1(oracle.all_but_one(A64, X64), m, n, p, bA, bC)
+    scale = _blocks_of_T1(oracle.error_scale(A64, X64, last_mode=1), m, n, p, bA, bC)
     e = float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel()))
     bound = TOL_FP32 if prec == P32 else tol_bf16(m)
     say("  rel err", e, "bound", bound)
     assert got.shape == ref.shape
     assert e <= bound
+    check_entries(got, ref, scale, prec, -(-n // bA) * bA)
 
 
 # ------------------------------------------------------------------ symmetrisation
@@ -582,12 +609,20 @@ def test_vectors_vs_oracle(m, n, b, V, dt):
     y, s, ws = st().sttsm_vectors(Ab, Xd, m, n, b)
     y2, s2, _ = st().sttsm_vectors(Ab, Xd, m, n, b, ws=ws)
     torch.cuda.synchronize()
-    Y, S = oracle.vectors(A.astype(np.float64), X.astype(np.float64))
-    ey = float(np.linalg.norm(y.double().cpu().numpy() - Y) / np.linalg.norm(Y))
-    es = float(np.linalg.norm(s.double().cpu().numpy() - S) / np.linalg.norm(S))
+    A64, X64 = A.astype(np.float64), X.astype(np.float64)
+    Y, S = oracle.vectors(A64, X64)
+    gy, gs = y.double().cpu().numpy(), s.double().cpu().numpy()
+    ey = float(np.linalg.norm(gy - Y) / np.linalg.norm(Y))
+    es = float(np.linalg.norm(gs - S) / np.linalg.norm(S))
     tol = TOL_FP32 if dt == "f32" else tol_bf16(m)
     say("vectors", m, n, b, V, dt, "rel err y", ey, "s", es)
     assert ey <= tol and es <= tol
+    # entry by entry: y_v sums up to n^(m-1) terms and s_v n^m terms in one
+    # FP32 accumulation each; the inputs are exact in the kernel's precision
+    sy = np.array([oracle.error_scale(A64, X64[v:v + 1], last_mode=1).ravel() for v in range(V)])
+    ss = np.array([oracle.error_scale(A64, X64[v:v + 1]).ravel()[0] for v in range(V)])
+    check_entries(gy, Y, sy, P32, n ** (m - 1), what="y")
+    check_entries(gs, S, ss, P32, n ** m, what="s")
     assert torch.equal(y, y2) and torch.equal(s, s2)
 
 
@@ -623,11 +658,13 @@ def test_rank_update_vs_oracle(case):
     C, _ = st().sttsm_rank_update(Ab, Xd, m, n, p, bA, bC, prec, rows, C=C0)
     torch.cuda.synchronize()
     got = C.double().cpu().numpy().reshape(-1, bC ** m)
-    ref = bcss_ref.pack(oracle.rank_update(A.astype(np.float64), X.astype(np.float64), bA, rows), bC)
+    A64, X64 = A.astype(np.float64), X.astype(np.float64)
+    ref = bcss_ref.pack(oracle.rank_update(A64, X64, bA, rows), bC)
     e = err(got, ref, m, p, bC)
     bound = {P32: TOL_FP32, PBF: tol_bf16(m), PX3F: TOL_X3_FIRST_FP32}[prec]
     say("  rel err", e, "bound", bound)
     assert e <= bound
+    check_entries(got, ref, bcss_ref.pack(oracle.error_scale(A64, X64), bC), prec, -(-n // bA) * bA)
     assert np.all(got[padding_mask(m, p, bC)] == 0.0)
 
 

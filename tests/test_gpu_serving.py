@@ -7,11 +7,9 @@ import pytest
 import oracle
 from oracle import bcss_ref
 import synth
-from gpu_util import say, tol_bf16
+from gpu_util import PBF, check_entries, reference, say, tol_bf16
 
 pytestmark = pytest.mark.gpu
-
-PBF = 1
 
 
 def st():
@@ -64,12 +62,14 @@ def test_served_results_match_plain_path_and_oracle():
         torch.cuda.synchronize()
         nb = st().bcss_num_blocks(m, -(-p // b))
         plain = Cp.double().cpu().numpy().reshape(nb, b ** m)
-        ref = bcss_ref.pack(oracle.chain(A.astype(np.float64), X.astype(np.float64)), b)
+        ref, S = reference(A, X, b)
         e_plain = bcss_ref.rel_frobenius_bcss(C.reshape(nb, -1), plain, m, p, b)
         e_ref = bcss_ref.rel_frobenius_bcss(C.reshape(nb, -1), ref, m, p, b)
         say("  req", (m, n, p, b), "vs plain", e_plain, "vs oracle", e_ref)
         assert e_ref <= tol_bf16(m)
         assert e_plain <= tol_bf16(m)
+        check_entries(C.reshape(nb, -1), ref, S, PBF, -(-n // b) * b)
+        assert np.array_equal(C.reshape(nb, -1), plain)
 
 
 def test_alone_equals_mix_bitwise():
