@@ -153,6 +153,30 @@ int sttsm(const bcss_layout *A, const void *A_dev, const void *X_dev, int64_t rs
           const bcss_layout *C, void *C_dev, int32_t prec, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * sttsm for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * operation, arguments, layouts and precision forms as sttsm, and the same
+ * kernels (bit-identical results), but no workspace argument: the X panels
+ * and temporaries, and the plan's index tables, live in one static device
+ * array of STTSM_NOALLOC_SCRATCH_BYTES (96 MiB; m = 3, n = p = 256, b = 16
+ * needs 68.5 MiB in the split form, the largest) that every GPU the library
+ * runs on holds until the process ends.
+ *
+ * The call allocates no device memory: the plan is built once per shape in
+ * host memory and cached; each call copies its index tables into the array
+ * on `stream` (hipMemcpyAsync) and launches the levels there.
+ * Errors: STTSM_EINVAL when the problem needs more scratch than the array
+ * holds (the message gives both sizes), plus those of sttsm.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * there; a call never reads a byte of it that the call has not written.
+ * Calls that overlap in time on one GPU (other streams or host threads)
+ * race on the array: order them on one stream.
+ */
+#define STTSM_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+int sttsm_noalloc(const bcss_layout *A, const void *A_dev, const void *X_dev, int64_t rs_x, int64_t cs_x,
+                  const bcss_layout *C, void *C_dev, int32_t prec, void *stream);
+
+/*
  * "All modes but one" (the related operation §2.5 names next to sttsm): the
  * tensor A x_1 X x_2 X ... x_{m-1} X, which multiplies every mode but mode 0
  * and is symmetric in modes 1..m-1.  It is the temporary T^(1) of the sttsm

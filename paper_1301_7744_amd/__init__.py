@@ -69,6 +69,7 @@ def load():
         "sttsm_vectors_flops": (i64, [L, i64]),
         "sttsm_workspace_bytes": (sz, [L, L, i32]),
         "sttsm": (ctypes.c_int, [L, vp, vp, i64, i64, L, vp, i32, vp, sz, vp]),
+        "sttsm_noalloc": (ctypes.c_int, [L, vp, vp, i64, i64, L, vp, i32, vp]),
         "sttsm_all_but_one": (ctypes.c_int, [L, vp, vp, i64, i64, L, vp, i32, vp, sz, vp]),
         "sttsm_all_but_one_elems": (i64, [L, L, i32]),
         "sttsm_rank_update": (ctypes.c_int, [L, vp, vp, i64, i64, L, vp, i32, i32, vp, sz, vp]),
@@ -105,7 +106,7 @@ def load():
 def exported_symbols():
     return ["bcss_num_blocks", "bcss_num_elems", "bcss_pack", "bcss_unpack", "bcss_fill_hashed", "bcss_symmetrize",
             "sttsm_flops", "sttsm_vectors", "sttsm_vectors_workspace_bytes", "sttsm_vectors_flops",
-            "sttsm_workspace_bytes", "sttsm", "sttsm_all_but_one", "sttsm_all_but_one_elems", "sttsm_rank_update",
+            "sttsm_workspace_bytes", "sttsm", "sttsm_noalloc", "sttsm_all_but_one", "sttsm_all_but_one_elems", "sttsm_rank_update",
             "sttsm_rank_update_workspace_bytes", "sttsm_workspace_temp", "sttsm_plan_info", "sttsm_profile_enable",
             "sttsm_profile_read", "sttsm_profile_disable", "sttsm_request_footprint", "sttsm_server_create",
             "sttsm_submit", "sttsm_poll", "sttsm_wait", "sttsm_fetch", "sttsm_server_stats", "sttsm_server_destroy",
@@ -295,6 +296,27 @@ def sttsm(A_bcss, X, m: int, n: int, p: int, bA: int, bC: int, prec: int = PREC_
     _check(load().sttsm(ctypes.byref(LA), _ptr(A_bcss), X.data_ptr(), X.stride(0), X.stride(1),
                         ctypes.byref(LC), _ptr(C), prec, _ptr(ws), ws.numel(), _stream(stream)))
     return C, ws
+
+
+NOALLOC_SCRATCH_BYTES = 96 << 20
+
+
+def sttsm_noalloc(A_bcss, X, m: int, n: int, p: int, bA: int, bC: int, C, prec: int = PREC_FP32, stream=None):
+    """C := [A; X, ..., X] into the caller's C (float32, BCSS) with no
+    workspace: the library's static device scratch array holds the
+    temporaries and tables.  Returns C."""
+    dt = _torch_dtype_code(A_bcss)
+    if X.dtype != A_bcss.dtype or X.dim() != 2 or tuple(X.shape) != (p, n):
+        raise ValueError("X must be a (p, n) tensor of A's dtype")
+    LA, LC = layout(m, n, bA, dt), layout(m, p, bC, F32)
+    if A_bcss.numel() < bcss_num_elems(m, n, bA, dt):
+        raise ValueError("A too small for its layout")
+    import torch
+    if C.numel() < bcss_num_elems(m, p, bC, F32) or C.dtype != torch.float32:
+        raise ValueError("C too small or not float32")
+    _check(load().sttsm_noalloc(ctypes.byref(LA), _ptr(A_bcss), X.data_ptr(), X.stride(0), X.stride(1),
+                                ctypes.byref(LC), _ptr(C), prec, _stream(stream)))
+    return C
 
 
 def sttsm_all_but_one(A_bcss, X, m: int, n: int, p: int, bA: int, bC: int, prec: int = PREC_FP32, T=None,

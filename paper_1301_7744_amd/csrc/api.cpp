@@ -326,10 +326,19 @@ int run_levels(const bcss_layout *A, const void *A_dev, const void *X_dev, int64
     const Plan *P = plan_get(key, &why);
     if (!P) return fail(STTSM_ENOMEM, why);
     if (ws_bytes < P->ws_bytes || (!ws && P->ws_bytes)) return fail(STTSM_EINVAL, "workspace too small");
+    return launch_levels(P, A, A_dev, X_dev, rs_x, cs_x, last_from_end, out, (char *)ws, nullptr,
+                         as_stream(stream));
+}
+
+}  // namespace
+
+namespace symt {
+
+int launch_levels(const Plan *P, const bcss_layout *A, const void *A_dev, const void *X_dev, int64_t rs_x,
+                  int64_t cs_x, int last_from_end, void *out, char *w, const char *tabs, hipStream_t s)
+{
     const int last = (int)P->stages.size() - 1 - last_from_end;
     if (last < 0) return fail(STTSM_EINVAL, "order too small for this operation");
-    hipStream_t s = as_stream(stream);
-    char *w = (char *)ws;
     float *x32 = P->xp_off[0] >= 0 ? (float *)(w + P->xp_off[0]) : nullptr;
     uint16_t *xhi = P->xp_off[1] >= 0 ? (uint16_t *)(w + P->xp_off[1]) : nullptr;
     uint16_t *xlo = P->xp_off[2] >= 0 ? (uint16_t *)(w + P->xp_off[2]) : nullptr;
@@ -343,6 +352,15 @@ int run_levels(const bcss_layout *A, const void *A_dev, const void *X_dev, int64
     for (int d = 0; d <= last; ++d) {
         const StagePlan &S = P->stages[d];
         StageArgs a = S.args;
+        if (tabs) {
+            const TabOff &t = P->tab_off[d];
+            a.groups = t.groups < 0 ? nullptr : (const GroupDesc *)(tabs + t.groups);
+            a.in_tab = t.in_tab < 0 ? nullptr : (const InEntry *)(tabs + t.in_tab);
+            a.tasks = t.tasks < 0 ? nullptr : (const Task *)(tabs + t.tasks);
+            a.fdig = t.fdig < 0 ? nullptr : (const int32_t *)(tabs + t.fdig);
+            a.fopart = t.fopart < 0 ? nullptr : (const int32_t *)(tabs + t.fopart);
+            a.zero_blk = t.zero < 0 ? nullptr : (const float *)(tabs + t.zero);
+        }
         a.in = S.in_ws < 0 ? A_dev : (const void *)(w + S.in_ws);
         a.out = d == last ? out : (void *)(w + S.out_ws);
         a.xp = slot_ptr[S.xp_slot];
@@ -359,7 +377,7 @@ int run_levels(const bcss_layout *A, const void *A_dev, const void *X_dev, int64
     return STTSM_OK;
 }
 
-}  // namespace
+}  // namespace symt
 
 extern "C" {
 

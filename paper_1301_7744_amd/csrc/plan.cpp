@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -720,6 +721,49 @@ const Plan *plan_get(const PlanKey &key, std::string *err)
     }
     const Plan *out = P.get();
     g_plans.emplace(dk, std::move(P));
+    return out;
+}
+
+static std::map<DevKey, std::unique_ptr<Plan>> g_host_plans;
+
+template <class T>
+static int64_t pack_table(const std::vector<T> &v, std::vector<unsigned char> *blob)
+{
+    if (v.empty()) return -1;
+    const size_t off = (blob->size() + 255) & ~(size_t)255;
+    blob->resize(off + v.size() * sizeof(T));
+    memcpy(blob->data() + off, v.data(), v.size() * sizeof(T));
+    return (int64_t)off;
+}
+
+const Plan *plan_get_host(const PlanKey &key, std::string *err)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        *err = "hipGetDevice failed";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    DevKey dk{dev, key};
+    auto it = g_host_plans.find(dk);
+    if (it != g_host_plans.end()) return it->second.get();
+    std::unique_ptr<Plan> P(new Plan);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    if (!plan_build_host(key, P.get(), err, cus)) return nullptr;
+    for (auto &S : P->stages) {
+        TabOff t;
+        t.groups = pack_table(S.groups, &P->tab_blob);
+        t.in_tab = pack_table(S.in_tab, &P->tab_blob);
+        t.tasks = pack_table(S.tasks, &P->tab_blob);
+        t.fdig = pack_table(S.fdig, &P->tab_blob);
+        t.fopart = pack_table(S.fopart, &P->tab_blob);
+        t.zero = pack_table(S.zero, &P->tab_blob);
+        P->tab_off.push_back(t);
+    }
+    P->tab_blob.resize((P->tab_blob.size() + 255) & ~(size_t)255);
+    const Plan *out = P.get();
+    g_host_plans.emplace(dk, std::move(P));
     return out;
 }
 

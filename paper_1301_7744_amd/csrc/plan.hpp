@@ -53,6 +53,11 @@ struct StagePlan {
     int64_t out_elems = 0;
 };
 
+// Byte offsets of one stage's tables inside Plan::tab_blob (-1: empty).
+struct TabOff {
+    int64_t groups = -1, in_tab = -1, tasks = -1, fdig = -1, fopart = -1, zero = -1;
+};
+
 struct Plan {
     int m = 0;
     int64_t n = 0, p = 0;
@@ -73,6 +78,11 @@ struct Plan {
     size_t ws_bytes = 0;
     int64_t flops = 0;
     std::vector<StagePlan> stages;
+    // Host-only plans (plan_get_host): every stage's tables packed into one
+    // buffer, each table 256-byte aligned, for a device region the caller
+    // provides; tab_off[d] gives stage d's offsets.
+    std::vector<unsigned char> tab_blob;
+    std::vector<TabOff> tab_off;
 };
 
 struct PlanKey {
@@ -87,6 +97,11 @@ struct PlanKey {
 // Builds (first call) or returns the cached plan; uploads device tables.
 // Returns nullptr and fills *err on failure.
 const Plan *plan_get(const PlanKey &key, std::string *err);
+// Host-only plan, built once per (device, key) and cached, with its tables
+// packed into tab_blob; allocates no device memory.  The stages' table
+// pointers in args are null: a launch rebases them onto a device copy of
+// tab_blob.
+const Plan *plan_get_host(const PlanKey &key, std::string *err);
 // Host part only (no device upload); for size queries.  Caller owns result.
 // cus: compute units of the device the plan runs on (the block-copy FP32
 // stages split tail tiles so that no CU gets more than one half tile extra).
