@@ -29,16 +29,12 @@ PEAK_VALU_FP32_TFLOPS = 78.6
 
 def measured_traffic(workload, prec, level):
     """HBM bytes per launch of a level's kernel from the committed rocprofv3
-    counter summary, or None when there is none or the kernel source has
-    changed since it was taken."""
-    import hashlib
+    counter summary, or None when there is none or the level kernels, the
+    plan or their shared types have changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (workload, prec))
-    src_name = "stage_bf16.hip" if prec == "bf16" else "kernels.hip"   # the file holding the level kernels
-    src = os.path.join(ROOT, "paper_1301_7744_amd", "csrc", src_name)
     try:
         d = json.load(open(path))
-        cur = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if d.get("source", "kernels.hip") != src_name or d.get("source_sha256", d.get("kernels_hip_sha256")) != cur:
+        if d.get("sources_sha256") != source_digest():
             return None
         e = d["per_level"][str(level)]
         return int(e["fetch_bytes"] + e["write_bytes"])
@@ -70,7 +66,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--prec", default="fp32")
     ap.add_argument("--workload", default="m3_n256_b16")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the CPU oracle: no cpu_baseline and no accuracy figures")
+    ap.add_argument("--no-bf16", action="store_true", help="FP32 runs: skip the bf16 block on the same workload")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--op", default="sttsm", choices=["sttsm", "all_but_one", "vectors", "rank_update"],
                     help="sttsm, the product in all modes but mode 0, batched vector products, or the "
@@ -428,6 +426,218 @@ def rank_update_bench(args):
     print(json.dumps(out), flush=True)
 
 
+# Relative error per operand of each precision form (the unit of the
+# entry-by-entry error scale): bf16 rounding, the two-term bf16 split of an
+# fp32 value, FP32 accumulation over Kpad terms (added in accuracy()).
+UNIT = {"fp32": 0.0, "bf16": 2.0 ** -9, "bf16x3_fp32": 2.0 ** -17, "bf16x3_bf16": 2.0 ** -9}
+DTYPE_NAME = {"fp32": "f32", "bf16": "bf16", "bf16x3_fp32": "bf16x3+f32", "bf16x3_bf16": "bf16x3+bf16"}
+
+
+def source_digest():
+    """sha256 over the sources that decide the level kernels' HBM traffic:
+    the kernels, the plan (tiles, task order, tail splits) and their shared
+    types."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "stage_bf16.hip", "plan.cpp", "common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1301_7744_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def measure(args, prec_name, A_np, X_np, op="sttsm", timing_steps=None):
+    """Times one precision form of the operation on the given inputs (K
+    graph replays with an event at every step boundary, then K eager steps
+    with per-level events) and returns its figures and the result."""
+    import numpy as np
+    import torch
+    import paper_1301_7744_amd as st
+    import synth
+    cfg = synth.workload(args.workload)
+    m, n, p, bA, bC = cfg["m"], cfg["n"], cfg["p"], cfg["bA"], cfg["bC"]
+    prec = st.PREC_NAMES[prec_name]
+    dev = torch.device("cuda:0")
+    steps = timing_steps or args.steps
+    if prec_name == "bf16":
+        # the bf16 form takes bf16 inputs; the oracle sees the same values
+        A_np, X_np = synth.round_to_bf16(A_np), synth.round_to_bf16(X_np)
+    tdt = torch.bfloat16 if prec_name == "bf16" else torch.float32
+    A_dense = torch.from_numpy(np.ascontiguousarray(A_np.ravel(order="F"))).to(tdt).to(dev)
+    X = torch.from_numpy(np.ascontiguousarray(X_np)).to(tdt).to(dev)
+    A = st.bcss_pack(A_dense, m, n, bA)
+    del A_dense
+    if op == "sttsm":
+        C, ws = st.sttsm(A, X, m, n, p, bA, bC, prec)
+        call = lambda: st.sttsm(A, X, m, n, p, bA, bC, prec, C=C, ws=ws)
+        nlev = m
+    else:
+        C, ws = st.sttsm_all_but_one(A, X, m, n, p, bA, bC, prec)
+        call = lambda: st.sttsm_all_but_one(A, X, m, n, p, bA, bC, prec, T=C, ws=ws)
+        nlev = m - 1
+    torch.cuda.synchronize()
+    levels = [st.sttsm_plan_info(m, n, p, bA, bC, prec, d, dtype=st.BF16 if prec_name == "bf16" else st.F32)
+              for d in range(nlev)]
+    flops = sum(lv["flops"] for lv in levels)
+    stream = torch.cuda.current_stream()
+
+    log("bench: %s warmup %d" % (prec_name, args.warmup))
+    for _ in range(args.warmup):
+        call()
+    torch.cuda.synchronize()
+
+    # Timed region 1 (the reported throughput): K steps, each one replay of
+    # a HIP graph holding one whole call (X panels and every level's
+    # kernel), synchronised on both sides, with an event at every step
+    # boundary (per-step times: median, p10, p90).  The graph removes the
+    # host's per-launch cost between the kernels; every replay does all the
+    # work.
+    graph = None
+    if not args.eager:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            call()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            call()
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+
+    def timed(step):
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        t = time.perf_counter()
+        ev[0].record(stream)
+        for i in range(steps):
+            step()
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) * 1e3 / steps
+        per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+        return ev[0].elapsed_time(ev[steps]) / steps, wall, per
+
+    C_graph = None
+    per = None
+    if graph is not None:
+        ms_step, wall_ms, per = timed(graph.replay)
+        C_graph = C.clone()
+    # Timed region 2: the same K steps launched eagerly, with HIP events
+    # recorded on the launch stream around each level's kernel (per-level
+    # kernel times for the roofline).
+    st.profile_enable(max(16, steps * m + 8))
+    eager_ms, eager_wall, eager_per = timed(call)
+    prof = st.profile_read(8)
+    st.profile_disable()
+    if graph is None:
+        ms_step, wall_ms, per = eager_ms, eager_wall, eager_per
+    else:
+        torch.cuda.synchronize()
+        if not torch.equal(C_graph, C):
+            raise RuntimeError("graph replay and eager launches gave different C")
+    log("bench: %s %.4f ms/step (%s; wall %.4f ms/step), eager %.4f ms/step" %
+        (prec_name, ms_step, "graph replay" if graph is not None else "eager", wall_ms, eager_ms))
+
+    # Dominant kernel: the level with the largest flop count (the first on
+    # ties); its roofline is MFMA or HBM, whichever bounds it by the model
+    # time = max(flops / MFMA peak, algorithmic bytes / HBM peak).
+    dom = max(range(nlev), key=lambda d: (levels[d]["flops"], -d))
+    dom_ms = prof[dom][0] / prof[dom][1]
+    peak = PEAK_TFLOPS[prec_name]
+    dom_bytes = level_bytes(m, n, p, bA, bC, prec_name, dom)
+    t_mfma = levels[dom]["flops"] / (peak * 1e12)
+    t_hbm = dom_bytes / (PEAK_HBM_GBS * 1e9)
+    if t_mfma >= t_hbm:
+        roof = {"bound": "mfma", "achieved": round(levels[dom]["flops"] / (dom_ms * 1e-3) / 1e12, 3), "peak": peak,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": round(dom_bytes / (dom_ms * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
+    roof["traffic"] = measured_traffic(args.workload, prec_name, dom)
+    roof["kernel"] = "level %d (%.3f GFLOP, %.1f MB algorithmic per launch)" % (dom, levels[dom]["flops"] / 1e9,
+                                                                                 dom_bytes / 1e6)
+    roof["kernel_us"] = round(dom_ms * 1e3, 3)
+    level_times = {str(d): round(prof[d][0] / prof[d][1] * 1e3, 3) for d in range(nlev) if d in prof}
+    res = {"prec": prec_name, "ms_per_step": round(ms_step, 5),
+           "step_ms": {"median": round(float(np.median(per)), 5), "p10": round(float(np.percentile(per, 10)), 5),
+                       "p90": round(float(np.percentile(per, 90)), 5)},
+           "tflops": round(flops / (ms_step * 1e-3) / 1e12, 3),
+           "mfma_roofline_frac": round(flops / (ms_step * 1e-3) / 1e12 / peak, 4),
+           "launch": "graph replay" if graph is not None else "eager",
+           "eager_ms_per_step": round(eager_ms, 5), "level_us": level_times, "roofline": roof,
+           "flops_per_step": flops}
+    if prec_name.startswith("bf16x3"):
+        # the split first level issues three bf16 products per flop of Table 2
+        issued = flops + 2 * levels[0]["flops"]
+        res["mfma_issued_flops_per_step"] = issued
+        res["mfma_issued_tflops"] = round(issued / (ms_step * 1e-3) / 1e12, 3)
+        res["mfma_issued_frac"] = round(issued / (ms_step * 1e-3) / 1e12 / peak, 4)
+    return res, dict(A=A, X=X, C=C, A_np=A_np, X_np=X_np, m=m, n=n, p=p, bA=bA, bC=bC, tdt=tdt, stream=stream)
+
+
+def accuracy(res, ctx, prec_name, op="sttsm"):
+    """Errors of the result against the FP64 oracle on the same input values:
+    relative Frobenius error over the dense tensor, max |error| / max |C|,
+    the largest |error_j| / (u S_j) with S_j the oracle's per-entry error
+    scale and u the form's relative error per operand, and the largest
+    difference between mirrored entries inside blocks with repeated indices
+    (computed one by one, §5.4), relative to max |C|."""
+    import itertools
+    import numpy as np
+    import oracle
+    import paper_1301_7744_amd as st
+    from oracle import bcss_ref
+    m, n, p, bA, bC = ctx["m"], ctx["n"], ctx["p"], ctx["bA"], ctx["bC"]
+    A64, X64 = ctx["A_np"].astype(np.float64), ctx["X_np"].astype(np.float64)
+    if op != "sttsm":
+        Tref = oracle.all_but_one(A64, X64)
+        nbar, pbar = -(-n // bA), -(-p // bC)
+        pad = np.zeros((nbar * bA,) + (pbar * bC,) * (m - 1))
+        pad[(slice(0, n),) + tuple(slice(0, p) for _ in range(m - 1))] = Tref
+        got = ctx["C"].double().cpu().numpy()
+        num = den = 0.0
+        for r, J in enumerate(bcss_ref.sorted_block_tuples(m - 1, pbar)):
+            for i in range(nbar):
+                sl = (slice(i * bA, (i + 1) * bA),) + tuple(slice(j * bC, (j + 1) * bC) for j in J)
+                ref = pad[sl].ravel(order="F")
+                num += float(np.sum((got[r, i] - ref) ** 2))
+                den += float(np.sum(ref ** 2))
+        res["rel_err_vs_fp64"] = float("%.3e" % (num / den) ** 0.5)
+        return
+    Cref, temps = oracle.chain(A64, X64, keep_temps=True)
+    S = oracle.error_scale(A64, X64, temps=temps)
+    del temps
+    nb = st.bcss_num_blocks(m, -(-p // bC))
+    got = ctx["C"].double().cpu().numpy().reshape(nb, bC ** m)
+    refb, Sb = bcss_ref.pack(Cref, bC), bcss_ref.pack(S, bC)
+    res["rel_err_vs_fp64"] = float("%.3e" % bcss_ref.rel_frobenius_bcss(got, refb, m, p, bC))
+    cmax = float(np.abs(Cref).max())
+    d = np.abs(got - refb)
+    res["max_abs_err_over_cmax"] = float("%.3e" % (d.max() / cmax))
+    u = UNIT[prec_name] + 2.0 ** -24 * (-(-n // bA) * bA) ** 0.5
+    nz = Sb > 0
+    res["max_err_over_u_scale"] = round(float((d[nz] / (u * Sb[nz])).max()), 3)
+    res["entry_bound"] = "|err_j| <= 16 u S_j, u = %.3g" % u
+    D = bcss_ref.unpack(got, m, p, bC)
+    asym = 0.0
+    for q in itertools.permutations(range(m)):
+        asym = max(asym, float(np.abs(D - np.transpose(D, q)).max()))
+    res["max_intrablock_asymmetry_over_cmax"] = float("%.3e" % (asym / cmax))
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -447,12 +657,8 @@ def main():
     import paper_1301_7744_amd as st
     import synth
 
-    cfg = synth.workload(args.workload)
-    m, n, p, bA, bC = cfg["m"], cfg["n"], cfg["p"], cfg["bA"], cfg["bC"]
-    prec = st.PREC_NAMES[args.prec]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-
     if args.calibrate_copy_mb > 0:
         src = torch.ones(args.calibrate_copy_mb * 2 ** 20 // 4, device=dev)
         dst = torch.empty_like(src)
@@ -463,130 +669,35 @@ def main():
 
     log("bench: generating inputs", args.workload)
     A_np, X_np = synth.make_config_inputs(args.workload)
-    if args.prec == "bf16":
-        # the bf16 form takes bf16 inputs; the oracle sees the same values
-        A_np, X_np = synth.round_to_bf16(A_np), synth.round_to_bf16(X_np)
-    tdt = torch.bfloat16 if args.prec == "bf16" else torch.float32
-    A_dense = torch.from_numpy(np.ascontiguousarray(A_np.ravel(order="F"))).to(tdt).to(dev)
-    X = torch.from_numpy(np.ascontiguousarray(X_np)).to(tdt).to(dev)
-    A = st.bcss_pack(A_dense, m, n, bA)
-    del A_dense
-    if args.op == "sttsm":
-        C, ws = st.sttsm(A, X, m, n, p, bA, bC, prec)
-        call = lambda: st.sttsm(A, X, m, n, p, bA, bC, prec, C=C, ws=ws)
-        nlev = m
-    else:
-        C, ws = st.sttsm_all_but_one(A, X, m, n, p, bA, bC, prec)
-        call = lambda: st.sttsm_all_but_one(A, X, m, n, p, bA, bC, prec, T=C, ws=ws)
-        nlev = m - 1
-    torch.cuda.synchronize()
-    levels = [st.sttsm_plan_info(m, n, p, bA, bC, prec, d, dtype=st.BF16 if args.prec == "bf16" else st.F32)
-              for d in range(nlev)]
-    flops = sum(lv["flops"] for lv in levels)
-    stream = torch.cuda.current_stream()
-
-    log("bench: warmup", args.warmup)
-    for _ in range(args.warmup):
-        call()
-    torch.cuda.synchronize()
-
-    # Timed region 1 (the reported throughput): K steps, each one replay of
-    # a HIP graph holding one whole sttsm call (X panels and every level's
-    # kernel), synchronised on both sides.  The graph removes the host's
-    # per-launch cost between the kernels; every replay does all the work.
-    graph = None
-    if not args.eager:
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            call()
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            call()
-        torch.cuda.synchronize()
-        for _ in range(args.warmup):
-            graph.replay()
-        torch.cuda.synchronize()
-
-    def timed(step):
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t = time.perf_counter()
-        e0.record(stream)
-        for _ in range(args.steps):
-            step()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / args.steps, (time.perf_counter() - t) * 1e3 / args.steps
-
-    eager_step = call
-    C_graph = None
-    if graph is not None:
-        ms_step, wall_ms = timed(graph.replay)
-        C_graph = C.clone()
-    # Timed region 2: the same K steps launched eagerly, with HIP events
-    # recorded on the launch stream around each level's kernel (per-level
-    # kernel times for the roofline).
-    st.profile_enable(max(16, args.steps * m + 8))
-    eager_ms, eager_wall = timed(eager_step)
-    prof = st.profile_read(8)
-    st.profile_disable()
-    if graph is None:
-        ms_step, wall_ms = eager_ms, eager_wall
-    else:
-        torch.cuda.synchronize()
-        if not torch.equal(C_graph, C):
-            raise RuntimeError("graph replay and eager launches gave different C")
-    log("bench: %.4f ms/step (%s; wall %.4f ms/step), eager %.4f ms/step" %
-        (ms_step, "graph replay" if graph is not None else "eager", wall_ms, eager_ms))
-    gflops = flops / (ms_step * 1e-3) / 1e9
-
-    # Dominant kernel: the level with the largest flop count (the first on
-    # ties); its roofline is MFMA or HBM, whichever bounds it by the model
-    # time = max(flops / MFMA peak, algorithmic bytes / HBM peak).
-    dom = max(range(nlev), key=lambda d: (levels[d]["flops"], -d))
-    dom_ms = prof[dom][0] / prof[dom][1]
-    peak = PEAK_TFLOPS[args.prec]
-    dom_bytes = level_bytes(m, n, p, bA, bC, args.prec, dom)
-    t_mfma = levels[dom]["flops"] / (peak * 1e12)
-    t_hbm = dom_bytes / (PEAK_HBM_GBS * 1e9)
-    if t_mfma >= t_hbm:
-        roof = {"bound": "mfma", "achieved": round(levels[dom]["flops"] / (dom_ms * 1e-3) / 1e12, 3), "peak": peak,
-                "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "hbm", "achieved": round(dom_bytes / (dom_ms * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s"}
-    roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
-    roof["traffic"] = measured_traffic(args.workload, args.prec, dom)
-    roof["kernel"] = "level %d (%.3f GFLOP, %.1f MB algorithmic per launch)" % (dom, levels[dom]["flops"] / 1e9,
-                                                                                 dom_bytes / 1e6)
-    roof["kernel_us"] = round(dom_ms * 1e3, 3)
-    level_times = {str(d): round(prof[d][0] / prof[d][1] * 1e3, 3) for d in range(nlev) if d in prof}
-
-    # Accuracy of this run against the FP64 oracle (also the CPU baseline).
+    res, ctx = measure(args, args.prec, A_np, X_np, op=args.op)
+    m, n, p, bA, bC = ctx["m"], ctx["n"], ctx["p"], ctx["bA"], ctx["bC"]
+    A, C, tdt, stream = ctx["A"], ctx["C"], ctx["tdt"], ctx["stream"]
+    ms_step = res["ms_per_step"]
+    flops = res["flops_per_step"]
     out = {
         "metric": ("sttsm" if args.op == "sttsm" else "sttsm all-modes-but-one") +
                   " GFLOP/s (symmetry-aware count, Table 2 of the paper)",
-        "value": round(gflops, 2),
+        "value": round(flops / (ms_step * 1e-3) / 1e9, 2),
         "unit": "GFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 5),
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16", "bf16x3_fp32": "bf16x3+f32", "bf16x3_bf16": "bf16x3+bf16"}[args.prec],
+        "dtype": DTYPE_NAME[args.prec],
         "data": synth.workload_data(args.workload),
         "config": {"workload": args.workload, "m": m, "n": n, "p": p, "bA": bA, "bC": bC, "prec": args.prec,
-                   "flops_per_step": flops, "mfma_roofline_frac": round(gflops / (peak * 1e3), 4),
-                   "launch": "graph replay" if graph is not None else "eager",
-                   "eager_ms_per_step": round(eager_ms, 5),
-                   "level_us": level_times},
-        "roofline": roof,
+                   "flops_per_step": flops, "mfma_roofline_frac": res["mfma_roofline_frac"],
+                   "launch": res["launch"], "eager_ms_per_step": res["eager_ms_per_step"],
+                   "level_us": res["level_us"]},
+        "step_ms": res["step_ms"],
+        "roofline": res["roofline"],
     }
+    for k in ("mfma_issued_flops_per_step", "mfma_issued_tflops", "mfma_issued_frac"):
+        if k in res:
+            out["config"][k] = res[k]
 
     # Pack and unpack (HBM-bound copies through the block layout), timed
     # apart from the step: K calls each, HIP events around the loop.
@@ -628,43 +739,50 @@ def main():
                              "frac": round(gbs / PEAK_HBM_GBS, 4)}
         del C2
 
+    # The bf16 form on the same workload, reported beside the FP32 line.
+    other = None
+    if args.op == "sttsm" and args.prec == "fp32" and not args.no_bf16:
+        other, octx = measure(args, "bf16", A_np, X_np)
+
     if not args.no_cpu_baseline:
         import oracle
-        from oracle import bcss_ref
+        log("bench: accuracy against the FP64 oracle")
+        accuracy(out, ctx, args.prec, args.op)
+        if other is not None:
+            accuracy(other, octx, "bf16")
         A64, X64 = A_np.astype(np.float64), X_np.astype(np.float64)
         log("bench: CPU oracle (dense chain, FP64)")
-        runs, t_cpu = 0, 0.0
-        Cref = None
         ref_fn = oracle.chain if args.op == "sttsm" else oracle.all_but_one
+        threads = oracle.num_threads()
+        runs, t_cpu = 0, 0.0
         while t_cpu < args.cpu_seconds and runs < 20:
             t = time.perf_counter()
-            Cref = ref_fn(A64, X64)
+            ref_fn(A64, X64)
             t_cpu += time.perf_counter() - t
             runs += 1
         cpu_gflops = flops / (t_cpu / runs) / 1e9
-        out["cpu_baseline"] = {"value": round(cpu_gflops, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
-                               "kind": "oracle",
-                               "sample": "full workload, dense FP64 mode-product chain, %d run(s), %.1f s" % (runs, t_cpu)}
-        if args.op == "sttsm":
-            nb = st.bcss_num_blocks(m, -(-p // bC))
-            got = C.double().cpu().numpy().reshape(nb, bC ** m)
-            err = bcss_ref.rel_frobenius_bcss(got, bcss_ref.pack(Cref, bC), m, p, bC)
-        else:
-            # T in its [J][ibar][block] layout against the oracle's dense T
-            nbar, pbar = -(-n // bA), -(-p // bC)
-            pad = np.zeros((nbar * bA,) + (pbar * bC,) * (m - 1))
-            pad[(slice(0, n),) + tuple(slice(0, p) for _ in range(m - 1))] = Cref
-            got = C.double().cpu().numpy()
-            num = den = 0.0
-            for r, J in enumerate(bcss_ref.sorted_block_tuples(m - 1, pbar)):
-                for i in range(nbar):
-                    sl = (slice(i * bA, (i + 1) * bA),) + tuple(slice(j * bC, (j + 1) * bC) for j in J)
-                    ref = pad[sl].ravel(order="F")
-                    num += float(np.sum((got[r, i] - ref) ** 2))
-                    den += float(np.sum(ref ** 2))
-            err = (num / den) ** 0.5
-        out["rel_err_vs_fp64"] = float("%.3e" % err)
-
+        # one thread, one run; and the literal sum (O1) on the small
+        # configuration m3_n16_b4, all threads
+        oracle.set_num_threads(1)
+        t = time.perf_counter()
+        ref_fn(A64, X64)
+        t_one = time.perf_counter() - t
+        oracle.set_num_threads(threads)
+        A1, X1 = synth.make_config_inputs("m3_n16_b4")
+        t = time.perf_counter()
+        oracle.direct_sum(A1.astype(np.float64), X1.astype(np.float64))
+        t_o1 = time.perf_counter() - t
+        dense_flops = 2 * sum(p ** (i + 1) * n ** (m - i) for i in range(m if args.op == "sttsm" else m - 1))
+        out["cpu_baseline"] = {
+            "value": round(cpu_gflops, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": "full workload, dense FP64 mode-product chain (%.1f GFLOP of dense work per run; the "
+                      "value divides Table 2's count by its time), %d run(s), %.1f s" % (dense_flops / 1e9, runs,
+                                                                                        t_cpu),
+            "cpu_model": cpu_model(), "one_thread_gflops": round(flops / t_one / 1e9, 3),
+            "one_thread_s": round(t_one, 2),
+            "o1_direct_sum_m3_n16_b4_s": round(t_o1, 4)}
+    if other is not None:
+        out["bf16"] = other
     print(json.dumps(out), flush=True)
 
 

@@ -264,10 +264,12 @@ int sttsm_workspace_temp(const bcss_layout *A, const bcss_layout *C, int32_t pre
  * nothing): for loop level `level` (0 forms T^(m-1), m-1 forms C) the number
  * of row groups (sorted C-block tuple of the level x unique output prefix of
  * the symmetric modes, Figure 6 with §6.3), of workgroup tasks, and the flops
- * the level performs (its term of Table 2).
+ * the level performs (its term of Table 2).  tile (5 entries, may be NULL):
+ * the level's kernel (0 generic, 1 FP32 block-copy, 2 bf16 block-copy), its
+ * tile rows and columns, K chunk and prefetch depth.  Any output may be NULL.
  */
 int sttsm_plan_info(const bcss_layout *A, const bcss_layout *C, int32_t prec, int32_t level,
-                    int64_t *groups, int64_t *tasks, int64_t *flops);
+                    int64_t *groups, int64_t *tasks, int64_t *flops, int32_t *tile);
 
 /*
  * Per-level timing for measurement tools.  While enabled, sttsm records a
@@ -338,8 +340,11 @@ int sttsm_poll(sttsm_server *s, uint64_t ticket, int32_t *state);
 int sttsm_wait(sttsm_server *s, uint64_t ticket, int64_t timeout_us, int32_t *state);
 
 /* Copies a finished request's C (bcss_num_elems(C) floats) to C_dst and
- * forgets the ticket.  EAGAIN if not finished, ENOTFOUND if unknown or
- * already fetched, EHIP if the request failed (the ticket is forgotten). */
+ * forgets the ticket; returns once the copy is complete (it runs on a
+ * stream of the server's own, without waiting for queued rounds), and only
+ * then gives C's arena region back.  EAGAIN if not finished, ENOTFOUND if
+ * unknown or already fetched, EHIP if the request failed (the ticket is
+ * forgotten). */
 int sttsm_fetch(sttsm_server *s, uint64_t ticket, void *C_dst, int32_t dst_is_host);
 
 /* Latency (submit -> done) percentiles and throughput of the requests

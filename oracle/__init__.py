@@ -19,6 +19,8 @@ Components
   entries     (O3)  many entries by the literal sum, each with its
                     root-sum-square of terms (the rounding-error scale)
   term_rss          that root-sum-square for every entry (O2 on A*A, X*X)
+  error_scale       per-entry 2-norm of the first-order sensitivities to every
+                    operand entry of the chain (the entry-by-entry error scale)
   closed_forms (O4) m=2 matrix identity, rank-1 / rank-r forms
   bcss_ref          independent BCSS enumerator, pack and unpack
   costs             storage / work counts by enumeration and by the paper's formulas
@@ -64,6 +66,8 @@ def _load():
         lib.oracle_chain.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int64, dp, dp, dp,
                                      ctypes.POINTER(dp)]
         lib.oracle_num_threads.argtypes = []
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_num_threads.restype = None
         for f in (lib.oracle_entry, lib.oracle_entries, lib.oracle_direct_sum, lib.oracle_mode_product,
                   lib.oracle_chain, lib.oracle_num_threads):
             f.restype = ctypes.c_int
@@ -90,6 +94,11 @@ def _check(A: np.ndarray, X: np.ndarray):
 def num_threads() -> int:
     """Threads the oracle's OpenMP loops use."""
     return _load().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's following OpenMP loops."""
+    _load().oracle_set_num_threads(int(n))
 
 
 def entry(A: np.ndarray, X: np.ndarray, j) -> float:

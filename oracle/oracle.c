@@ -206,6 +206,18 @@ int oracle_chain(int m, int64_t n, int64_t p, const double *A, const double *X,
     return 0;
 }
 
+/* Sets the number of OpenMP threads of the following calls (n >= 1); a
+ * no-op when built without OpenMP. */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Number of OpenMP threads the oracle runs on (1 when built without OpenMP). */
 int oracle_num_threads(void)
 {

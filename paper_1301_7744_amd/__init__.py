@@ -77,7 +77,7 @@ def load():
         "sttsm_workspace_temp": (ctypes.c_int, [L, L, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(i32),
                                                 ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "sttsm_plan_info": (ctypes.c_int, [L, L, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i64),
-                                           ctypes.POINTER(i64)]),
+                                           ctypes.POINTER(i64), ctypes.POINTER(i32)]),
         "sttsm_profile_enable": (ctypes.c_int, [i32]),
         "sttsm_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32,
                                               ctypes.POINTER(i64)]),
@@ -185,9 +185,11 @@ def sttsm_workspace_temp(m: int, n: int, p: int, bA: int, bC: int, prec: int, k:
 
 def sttsm_plan_info(m: int, n: int, p: int, bA: int, bC: int, prec: int, level: int, dtype: int = F32) -> dict:
     g, t, f = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    tile = (ctypes.c_int32 * 5)()
     _check(load().sttsm_plan_info(ctypes.byref(layout(m, n, bA, dtype)), ctypes.byref(layout(m, p, bC)), prec,
-                                  level, ctypes.byref(g), ctypes.byref(t), ctypes.byref(f)))
-    return dict(groups=g.value, tasks=t.value, flops=f.value)
+                                  level, ctypes.byref(g), ctypes.byref(t), ctypes.byref(f), tile))
+    kernel = ("generic", "fp32_block_copy", "bf16_block_copy")[tile[0]]
+    return dict(groups=g.value, tasks=t.value, flops=f.value, kernel=kernel, tile=tuple(tile[1:]))
 
 
 # ------------------------------------------------------------------ operations

@@ -105,6 +105,11 @@ int make_key(const bcss_layout *A, const bcss_layout *C, int32_t prec, PlanKey *
     key->in_dtype = A->dtype == STTSM_F32 ? F32 : BF16;
     const char *gen = getenv("STTSM_GENERIC_KERNELS");
     key->generic_only = gen && gen[0] == '1';
+    key->overrides.clear();
+    for (const char *name : {"STTSM_FAST_TILE", "STTSM_BF16_TILE", "STTSM_NARROW_MT", "STTSM_WIDE_MT"}) {
+        const char *v = getenv(name);
+        if (v && *v) key->overrides += std::string(name) + "=" + v + ";";
+    }
     return STTSM_OK;
 }
 
@@ -291,7 +296,7 @@ int sttsm_workspace_temp(const bcss_layout *A, const bcss_layout *C, int32_t pre
 }
 
 int sttsm_plan_info(const bcss_layout *A, const bcss_layout *C, int32_t prec, int32_t level, int64_t *groups,
-                    int64_t *tasks, int64_t *flops)
+                    int64_t *tasks, int64_t *flops, int32_t *tile)
 {
     PlanKey key;
     int rc = make_key(A, C, prec, &key);
@@ -304,6 +309,13 @@ int sttsm_plan_info(const bcss_layout *A, const bcss_layout *C, int32_t prec, in
     if (groups) *groups = (int64_t)S.groups.size();
     if (tasks) *tasks = (int64_t)S.tasks.size();
     if (flops) *flops = S.flops;
+    if (tile) {
+        tile[0] = S.fast_bf16 ? 2 : S.fast ? 1 : 0;
+        tile[1] = S.tile.MT;
+        tile[2] = S.tile.NT;
+        tile[3] = S.tile.KT;
+        tile[4] = S.tile.PD;
+    }
     return STTSM_OK;
 }
 

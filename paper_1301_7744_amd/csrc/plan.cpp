@@ -63,7 +63,8 @@ bool PlanKey::operator<(const PlanKey &o) const
     if (prec != o.prec) return prec < o.prec;
     if (in_dtype != o.in_dtype) return in_dtype < o.in_dtype;
     if (grouped != o.grouped) return grouped < o.grouped;
-    return generic_only < o.generic_only;
+    if (generic_only != o.generic_only) return generic_only < o.generic_only;
+    return overrides < o.overrides;
 }
 
 static int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }

@@ -91,6 +91,10 @@ struct PlanKey {
     int bA, bC, prec, in_dtype;
     bool generic_only = false;   // force the generic staging kernel (testing)
     bool grouped = false;        // tiles of the grouped kernel (serving)
+    // The measurement overrides of the tile choice in force when the plan was
+    // built (STTSM_FAST_TILE, STTSM_BF16_TILE, STTSM_NARROW_MT,
+    // STTSM_WIDE_MT), so that a plan is never reused under other overrides.
+    std::string overrides;
     bool operator<(const PlanKey &o) const;
 };
 

@@ -156,6 +156,9 @@ struct sttsm_server {
     // device side of the rounds: two slots, so that the next round is formed
     // and queued while the previous one runs
     hipStream_t stream = nullptr;
+    // copies of finished results out of the arena (sttsm_fetch); its own
+    // stream, so that a fetch never waits behind queued rounds
+    hipStream_t fetch_stream = nullptr;
     struct Slot {
         hipEvent_t ev = nullptr;
         StageArgs *d_stages = nullptr;
@@ -533,6 +536,10 @@ int sttsm_server_create(void *arena, size_t arena_bytes, int32_t max_inflight, s
         S->grid = 2 * cus;
     if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess)
         return fail(STTSM_EHIP, "hipStreamCreate failed");
+    if (hipStreamCreateWithFlags(&S->fetch_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(S->stream);
+        return fail(STTSM_EHIP, "hipStreamCreate failed");
+    }
     for (auto &sl : S->slot)
         if (hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess ||
             hipMalloc((void **)&sl.d_heads, kLaunchClasses * sizeof(int)) != hipSuccess) {
@@ -541,6 +548,7 @@ int sttsm_server_create(void *arena, size_t arena_bytes, int32_t max_inflight, s
                 if (s2.d_heads) (void)hipFree(s2.d_heads);
             }
             (void)hipStreamDestroy(S->stream);
+            (void)hipStreamDestroy(S->fetch_stream);
             return fail(STTSM_EHIP, "server: cannot create event or queue heads");
         }
     sttsm_server *raw = S.release();
@@ -618,13 +626,22 @@ int sttsm_fetch(sttsm_server *S, uint64_t ticket, void *C_dst, int32_t dst_is_ho
         return fail(STTSM_EHIP, "request failed: " + S->fatal);
     }
     if (q->state != STTSM_DONE) return fail(STTSM_EAGAIN, "not finished");
-    const size_t bytes = (size_t)bcss_num_elems(&q->r.C) * 4;
-    const hipError_t e =
-        hipMemcpy(C_dst, q->C, bytes, dst_is_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice);
-    release_c(S, q);
+    // Take the request out of the table (a second fetch of the ticket now
+    // finds nothing), copy without the lock, and give C's region back only
+    // once the copy has completed: until then no admitted request can be
+    // placed over it.
+    std::unique_ptr<Req> own = std::move(it->second);
     S->all.erase(it);
+    lk.unlock();
+    const size_t bytes = (size_t)bcss_num_elems(&q->r.C) * 4;
+    hipError_t e = hipMemcpyAsync(C_dst, q->C, bytes, dst_is_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                                  S->fetch_stream);
+    const hipError_t e2 = hipStreamSynchronize(S->fetch_stream);
+    if (e == hipSuccess) e = e2;
+    lk.lock();
+    release_c(S, q);
     S->cv_work.notify_one();   // freed arena may admit waiting requests
-    if (e != hipSuccess) return fail(STTSM_EHIP, "copy of C failed");
+    if (e != hipSuccess) return fail(STTSM_EHIP, std::string("copy of C failed: ") + hipGetErrorString(e));
     return STTSM_OK;
 }
 
@@ -674,7 +691,9 @@ int sttsm_server_destroy(sttsm_server *S)
         if (sl.h_tasks) (void)hipHostFree(sl.h_tasks);
         (void)hipEventDestroy(sl.ev);
     }
+    (void)hipStreamSynchronize(S->fetch_stream);
     (void)hipStreamDestroy(S->stream);
+    (void)hipStreamDestroy(S->fetch_stream);
     delete S;
     return STTSM_OK;
 }

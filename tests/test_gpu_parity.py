@@ -369,15 +369,16 @@ def test_block_copy_and_generic_kernels(m, n, p, bA, bC, generic, monkeypatch):
 
 # Every instantiated tile of the FP32 block-copy kernel that a level can
 # take (STTSM_FAST_TILE, one entry per level, empty = default): prefetch
-# depths 1-4, K chunks of 16 and 32, 32- to 128-column tiles.  The plan cache
-# is keyed by shape, not by the tile choice, so each case has its own n, p.
+# depths 1-4, K chunks of 16 and 32, 32- to 128-column tiles.  The first
+# level (k = m-1) takes whole 256-row block rows only.  Each test checks,
+# through sttsm_plan_info, that the plan took the requested tile.
 FAST_TILE_CASES = [
     ("256x64x16x2,128x128x16x2,128x64x16x2", 3, 101, 71),
     (",128x128x16x3,128x64x16x3", 3, 103, 75),
     (",128x64x16x4,128x64x16x4", 3, 105, 81),
     ("256x32x16x1,128x32x16x1,128x32x16x2", 3, 99, 83),
     ("256x128x16x1,128x64x32x1,128x64x32x1", 3, 97, 87),
-    ("128x128x16x1,128x64x16x2,256x64x16x1", 3, 94, 90),
+    (",128x64x16x2,256x64x16x1", 3, 94, 90),
     ("256x64x16x2,256x64x16x1,256x64x16x2", 5, 11, 9),
 ]
 
@@ -389,6 +390,11 @@ def test_block_copy_tile_variants(tiles, m, n, p, monkeypatch):
     monkeypatch.setenv("STTSM_FAST_TILE", tiles)
     b = 16 if m == 3 else 4
     say("tile variant", tiles, m, n, p, b)
+    for d, want in enumerate(tiles.split(",")):
+        if want:
+            info = st().sttsm_plan_info(m, n, p, b, b, P32, d)
+            assert info["kernel"] == "fp32_block_copy"
+            assert info["tile"] == tuple(int(v) for v in want.split("x")), (d, info)
     A = synth.symmetric_uniform(m, n, (m, n, p, 93))
     X = synth.change_of_basis(p, n, (m, n, p, 94))
     got = run(A, X, b, b, P32)
@@ -463,6 +469,13 @@ def test_bf16_tile_variants(tiles, m, n, p, b, monkeypatch):
     monkeypatch.delenv("STTSM_GENERIC_KERNELS", raising=False)
     monkeypatch.setenv("STTSM_BF16_TILE", tiles)
     say("bf16 tile variant", tiles, m, n, p, b)
+    parts = tiles.split(",")
+    for d in range(m):
+        want = parts[0] if len(parts) == 1 else (parts[d] if d < len(parts) else "")
+        if want:
+            info = st().sttsm_plan_info(m, n, p, b, b, PBF, d, dtype=st().BF16)
+            assert info["kernel"] == "bf16_block_copy"
+            assert info["tile"][1:] == tuple(int(v) for v in want.split("x")), (d, info)
     A = synth.round_to_bf16(synth.symmetric_uniform(m, n, (m, n, p, 95)))
     X = synth.round_to_bf16(synth.change_of_basis(p, n, (m, n, p, 96)))
     got = run(A, X, b, b, PBF, dtype=torch.bfloat16)
