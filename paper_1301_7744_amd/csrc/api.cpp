@@ -106,7 +106,8 @@ int make_key(const bcss_layout *A, const bcss_layout *C, int32_t prec, PlanKey *
     const char *gen = getenv("STTSM_GENERIC_KERNELS");
     key->generic_only = gen && gen[0] == '1';
     key->overrides.clear();
-    for (const char *name : {"STTSM_FAST_TILE", "STTSM_BF16_TILE", "STTSM_NARROW_MT", "STTSM_WIDE_MT"}) {
+    for (const char *name : {"STTSM_FAST_TILE", "STTSM_BF16_TILE", "STTSM_NARROW_MT", "STTSM_WIDE_MT",
+                             "STTSM_BF16_XRES"}) {
         const char *v = getenv(name);
         if (v && *v) key->overrides += std::string(name) + "=" + v + ";";
     }
@@ -310,7 +311,7 @@ int sttsm_plan_info(const bcss_layout *A, const bcss_layout *C, int32_t prec, in
     if (tasks) *tasks = (int64_t)S.tasks.size();
     if (flops) *flops = S.flops;
     if (tile) {
-        tile[0] = S.fast_bf16 ? 2 : S.fast ? 1 : 0;
+        tile[0] = S.fast_bf16 ? (S.tile.xres ? 3 : 2) : S.fast ? 1 : 0;
         tile[1] = S.tile.MT;
         tile[2] = S.tile.NT;
         tile[3] = S.tile.KT;
@@ -372,6 +373,7 @@ int launch_levels(const Plan *P, const bcss_layout *A, const void *A_dev, const 
             a.fdig = t.fdig < 0 ? nullptr : (const int32_t *)(tabs + t.fdig);
             a.fopart = t.fopart < 0 ? nullptr : (const int32_t *)(tabs + t.fopart);
             a.zero_blk = t.zero < 0 ? nullptr : (const float *)(tabs + t.zero);
+            a.xrec = t.xrec < 0 ? nullptr : (const XresRec *)(tabs + t.xrec);
         }
         a.in = S.in_ws < 0 ? A_dev : (const void *)(w + S.in_ws);
         a.out = d == last ? out : (void *)(w + S.out_ws);
@@ -379,7 +381,7 @@ int launch_levels(const Plan *P, const bcss_layout *A, const void *A_dev, const 
         a.xp_lo = S.xp_lo_slot >= 0 ? slot_ptr[S.xp_lo_slot] : nullptr;
         const long slot = prof_slot(S.d);
         if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot], s);
-        const int lrc = S.fast_bf16 ? launch_stage_bf16(a, S.tile.NT, S.tile.KT, S.tile.PD, s)
+        const int lrc = S.fast_bf16 ? launch_stage_bf16(a, S.tile.NT, S.tile.KT, S.tile.PD, S.tile.xres, s)
                         : S.fast  ? launch_stage_fast(a, S.tile.MT, S.tile.NT, S.tile.KT, S.tile.PD, S.d == 0, s)
                                   : launch_stage(a, S.compute, S.tile.MT, S.tile.NT, S.d == 0, s);
         if (lrc)

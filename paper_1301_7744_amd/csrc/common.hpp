@@ -66,6 +66,20 @@ struct VecEntry {
     int32_t s[kMaxOrder];
 };
 
+// One task of the X-resident bf16 kernel with everything its prologue
+// needs in one record: the element offsets of the group's nbar <= 16 input
+// blocks, their insertion positions (2 bits each), the N tile's first
+// column, the M tile, and the group's output placement.
+struct XresRec {
+    int64_t off[16];
+    int64_t out_base;
+    int64_t out_jstride;
+    int32_t q_bits;
+    int32_t n0;
+    int32_t mt;
+    int32_t jcount;
+};
+
 // Launch-wide parameters of one stage (kernel argument, passed by value).
 struct StageArgs {
     const void *in;          // input tensor (A in BCSS, or T^(k+1))
@@ -120,6 +134,8 @@ struct StageArgs {
     // Generic kernel with an fp32 output: 1 adds the tile's sums to what the
     // output holds (the rank-update form's passes after the first), 0 stores.
     int32_t accumulate;
+    // X-resident bf16 kernel: one record per task, in task order.
+    const XresRec *xrec;
 };
 
 

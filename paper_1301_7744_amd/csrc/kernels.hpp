@@ -30,7 +30,9 @@ bool fast_supported(int m, int nbar);
 bool bf16_fast_supported(int m, int bA, int bC, int nbar);
 void bf16_fast_tile(int b, int *MT, int *NT, int *KT, int *PD);   // the default tile
 bool bf16_tile_supported(int b, int NT, int KT, int PD);
-int launch_stage_bf16(const StageArgs &a, int NT, int KT, int PD, hipStream_t s);
+int launch_stage_bf16(const StageArgs &a, int NT, int KT, int PD, bool xres, hipStream_t s);
+// Whether the X-resident bf16 form applies: b = 16, Kpad <= 256, bf16 input.
+bool bf16_xres_supported(int b, int Kpad, bool bf16_input);
 int launch_grouped_bf16(int m, int b, int k, const StageArgs *d_stages, const GroupedTask *d_tasks, int ntasks,
                         int *d_head, int grid, hipStream_t s);
 // In-place symmetrisation of the blocks with repeated indices (symmetrize.hip).

@@ -101,6 +101,39 @@ static TileCfg choose_tile(int Mblk)
 //    of tiles the dispatch order gives each slot; list position 8*l + x
 //    holds the l-th task of XCD x.
 // cost(t) is the work of tile t.
+// Tasks grouped by a locality key per row group, the keys dealt to the 8
+// XCDs (largest task count first, to the least-loaded XCD), then
+// interleaved so that task t runs on XCD t % 8 (workgroups are dispatched
+// to the XCDs in turn).  Groups with equal keys read the same input blocks,
+// so each block is fetched into one XCD's L2 (or two, at the first level).
+static void order_tasks_by_key(std::vector<Task> *tasks, const std::vector<int64_t> &group_key)
+{
+    constexpr int kXcd = 8;
+    std::map<int64_t, std::vector<Task>> by_key;
+    for (const Task &t : *tasks) by_key[group_key[t.group]].push_back(t);
+    std::vector<std::pair<size_t, int64_t>> sizes;
+    for (auto &kv : by_key) sizes.push_back({kv.second.size(), kv.first});
+    std::stable_sort(sizes.begin(), sizes.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+    std::vector<std::vector<Task>> bins(kXcd);
+    std::vector<size_t> load(kXcd, 0);
+    for (const auto &sz : sizes) {
+        int best = 0;
+        for (int x = 1; x < kXcd; ++x)
+            if (load[x] < load[best]) best = x;
+        const auto &v = by_key[sz.second];
+        bins[best].insert(bins[best].end(), v.begin(), v.end());
+        load[best] += v.size();
+    }
+    std::vector<Task> out;
+    out.reserve(tasks->size());
+    size_t longest = 0;
+    for (auto &bn : bins) longest = std::max(longest, bn.size());
+    for (size_t l = 0; l < longest; ++l)
+        for (int x = 0; x < kXcd; ++x)
+            if (l < bins[x].size()) out.push_back(bins[x][l]);
+    tasks->swap(out);
+}
+
 template <class Cost>
 static void order_tasks_for_xcds(std::vector<Task> *tasks, Cost cost, int cus, bool split);
 
@@ -470,6 +503,23 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err, int cus)
             int ont, okt, opd;
             if (!key.grouped && bf16_tile_override(d, &ont, &okt, &opd) && bf16_tile_supported(bA, ont, okt, opd))
                 S.tile = TileCfg{tmt, ont, 0, 0, okt, opd};
+            // The X-resident form takes the default b = 16 tile when the
+            // input is bf16 and a whole X panel row fits its LDS slice, with
+            // 96-column tiles (at m3_n256_b16 every level then has at most
+            // 512 tasks, one per resident workgroup).  STTSM_BF16_XRES=0
+            // keeps the chunk-staged kernel; "NTxPD" (NT 64, 96 or 128, PD
+            // 2 or 4) picks another tile, for measurement.
+            const char *xe = getenv("STTSM_BF16_XRES");
+            int xnt = 96, xpd = 2;
+            const bool xoff = xe && *xe && atoi(xe) == 0;
+            if (xe && *xe && !xoff && sscanf(xe, "%dx%d", &xnt, &xpd) != 2) xnt = 96, xpd = 2;
+            if ((xnt != 64 && xnt != 96 && xnt != 128) || (xpd != 2 && xpd != 4)) xnt = 96, xpd = 2;
+            if (!key.grouped && !xoff && bf16_xres_supported(bA, (int)P->Kpad, in_dt == BF16) &&
+                S.tile.NT == tnt && S.tile.KT == tkt && S.tile.PD == tpd) {
+                S.tile.xres = true;
+                S.tile.NT = xnt;
+                S.tile.PD = xpd;
+            }
         }
         for (int j = 0; j < m; ++j) {
             a.ext_in[j] = ext_in[j];
@@ -640,12 +690,47 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err, int cus)
             order_tasks_for_xcds(&S.tasks, [&](const Task &t) -> int64_t {
                 return (int64_t)std::min(MT, Mblk - t.mt * MT) * ((t.ncol + 31) / 32 * 32 + 16);
             }, std::max(cus / 8, 1), true);
+        } else if (S.tile.xres) {
+            // Locality key of a row group: below the first level the groups
+            // of one C-block tuple J' read only that tuple's slab of the
+            // input temporary; at the first level a stored A block is read
+            // by the prefixes it contains, whose largest indices take at
+            // most two values, so the key is the prefix's largest index.
+            std::vector<int64_t> key_of(S.groups.size());
+            for (int64_t jp = 0; jp < nJp; ++jp)
+                for (int64_t si = 0; si < nS; ++si)
+                    key_of[jp * nS + si] = d > 0 ? jp : (k > 0 ? Ss[si * k + k - 1] : 0);
+            order_tasks_by_key(&S.tasks, key_of);
         } else {
             order_tasks_group_major(&S.tasks);
         }
         if (mtiles > 32767 || (int64_t)P->Ppad / S.tile.NT > 32767 || S.tasks.size() > (size_t)INT32_MAX) {
             *err = "too many tasks";
             return false;
+        }
+        if (S.tile.xres) {
+            // One record per task, in the final task order.
+            if (nbar > 16) {
+                *err = "X-resident kernel: more than 16 input blocks";
+                return false;
+            }
+            S.xrec.resize(S.tasks.size());
+            for (size_t t = 0; t < S.tasks.size(); ++t) {
+                const Task &tk = S.tasks[t];
+                const GroupDesc &g = S.groups[tk.group];
+                XresRec r{};
+                for (int i = 0; i < nbar; ++i) {
+                    const InEntry &e = S.in_tab[(size_t)g.in_row + i];
+                    r.off[i] = e.off;
+                    r.q_bits |= (e.q & 3) << (2 * i);
+                }
+                r.out_base = g.out_base;
+                r.out_jstride = g.out_jstride;
+                r.n0 = tk.nt * S.tile.NT;
+                r.mt = tk.mt;
+                r.jcount = g.jcount;
+                S.xrec[t] = r;
+            }
         }
         a.ntasks = (int32_t)S.tasks.size();
         S.in_ws = d == 0 ? -1 : P->temp_off[k + 1];
@@ -711,8 +796,10 @@ const Plan *plan_get(const PlanKey &key, std::string *err)
     for (auto &S : P->stages) {
         if (!upload(S.groups, &S.d_groups, err) || !upload(S.in_tab, &S.d_in_tab, err) ||
             !upload(S.tasks, &S.d_tasks, err) || !upload(S.fdig, &S.d_fdig, err) ||
-            !upload(S.fopart, &S.d_fopart, err) || !upload(S.zero, &S.d_zero, err))
+            !upload(S.fopart, &S.d_fopart, err) || !upload(S.zero, &S.d_zero, err) ||
+            !upload(S.xrec, &S.d_xrec, err))
             return nullptr;   // tables of a failed plan are leaked, never used
+        S.args.xrec = S.d_xrec;
         S.args.zero_blk = S.d_zero;
         S.args.fdig = S.d_fdig;
         S.args.fopart = S.d_fopart;
@@ -760,6 +847,7 @@ const Plan *plan_get_host(const PlanKey &key, std::string *err)
         t.fdig = pack_table(S.fdig, &P->tab_blob);
         t.fopart = pack_table(S.fopart, &P->tab_blob);
         t.zero = pack_table(S.zero, &P->tab_blob);
+        t.xrec = pack_table(S.xrec, &P->tab_blob);
         P->tab_off.push_back(t);
     }
     P->tab_blob.resize((P->tab_blob.size() + 255) & ~(size_t)255);

@@ -24,6 +24,7 @@ struct TileCfg {
     int MT, NT, WM, WN;
     int KT = 16;   // K chunk of the block-copy kernel
     int PD = 1;    // its prefetch depth (register sets of staged loads)
+    bool xres = false;   // bf16 block-copy, b = 16: the X-resident persistent form
 };
 
 struct StagePlan {
@@ -38,11 +39,13 @@ struct StagePlan {
     std::vector<InEntry> in_tab;
     std::vector<Task> tasks;
     std::vector<int32_t> fdig, fopart;   // block-copy kernel tables (see StageArgs)
+    std::vector<XresRec> xrec;           // X-resident bf16 kernel: per task record
     // Device copies (owned by the plan).
     GroupDesc *d_groups = nullptr;
     InEntry *d_in_tab = nullptr;
     Task *d_tasks = nullptr;
     int32_t *d_fdig = nullptr, *d_fopart = nullptr;
+    XresRec *d_xrec = nullptr;
     std::vector<float> zero;   // block-copy FP32 kernel: one zero input block
     float *d_zero = nullptr;
     // Where the operands live: -1 means the caller's A (input) or C (output),
@@ -55,7 +58,7 @@ struct StagePlan {
 
 // Byte offsets of one stage's tables inside Plan::tab_blob (-1: empty).
 struct TabOff {
-    int64_t groups = -1, in_tab = -1, tasks = -1, fdig = -1, fopart = -1, zero = -1;
+    int64_t groups = -1, in_tab = -1, tasks = -1, fdig = -1, fopart = -1, zero = -1, xrec = -1;
 };
 
 struct Plan {

@@ -345,8 +345,14 @@ __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, B
     // and each store waits only for its own stage.  The extra chunks add
     // zeros.
     const int nch_pad = (nch + PD - 1) / PD * PD;
+    // The stages go out oldest first: the scheduler must not reorder them,
+    // or the first store would wait for every load in flight, and with it
+    // the loop (whose waits are merged at its head) on every pass.
 #pragma unroll
-    for (int u = 0; u < PD; ++u) load_chunk(u, u);
+    for (int u = 0; u < PD; ++u) {
+        load_chunk(u, u);
+        __builtin_amdgcn_sched_barrier(0);
+    }
     for (int c0 = 0; c0 < nch_pad; c0 += PD) {
 #pragma unroll
         for (int u = 0; u < PD; ++u) {
@@ -451,6 +457,306 @@ __global__ __launch_bounds__(256, 2) void grouped_fast_bf16(const StageArgs *__r
     }
 }
 
+// ---------------------------------------------------------------------------
+// X-resident form for b = 16 (the tile contract of stage_fast_bf16 with one
+// block per K chunk; every output entry gets the same MFMA sequence on the
+// same operands, hence the same bits).  Differences:
+//  - the tile's XNT rows of the X panel (all Kpad <= 256 k values) are
+//    staged in LDS at the start of a task, so the chunk loop stages only the
+//    input block;
+//  - each task has one record (the input blocks' offsets and permutations,
+//    the output placement), loaded one task ahead, instead of a chain of
+//    task -> row group -> input table reads;
+//  - every thread computes, once per M tile, the global and LDS offsets of
+//    its two 16-byte vectors for each insertion position q, packed into
+//    64-bit registers, so a chunk costs a shift, the load and the store;
+//  - the workgroups are persistent over the plan's task order (task t on
+//    workgroup t mod gridDim.x);
+//  - each wave computes 64 rows x XNT columns (2 x XNT/32 MFMA tiles).
+// Measured at m3_n256_b16: 96-column tiles (at most 512 tasks per level,
+// one per resident workgroup) take the step from 64.5 to 57.4 us; 64 columns
+// match the chunk-staged kernel, 128 columns (one workgroup per CU) are
+// slower.  Kept below 64 KB of LDS: workgroups whose per-thread arrays the
+// compiler had moved into LDS (70.8 KB) spent 8-9 us before their first
+// instruction past the prologue's barrier.
+constexpr int kXresMaxK = 256;             // largest Kpad the resident X slice holds
+constexpr int kXresXS = kXresMaxK + 8;     // its row stride (bf16)
+
+template <int M, int K, int XNT>
+struct XresSmem {
+    using C = Bf16Cfg<M, 16, K, 64, 16>;
+    __attribute__((aligned(16))) u16 s_x[XNT * kXresXS];
+    union {
+        __attribute__((aligned(16))) u16 s_in[2][C::IN_ELEMS];
+        __attribute__((aligned(16))) u16 s_out[4][32 * kOutRow];
+    };
+    int64_t s_rec[sizeof(XresRec) / 8];   // the current task's record
+};
+
+constexpr int kXresRecWords = (int)(sizeof(XresRec) / 8);
+static_assert(sizeof(XresRec) % 8 == 0 && kXresRecWords <= 64, "a record is a few 8-byte words");
+
+template <int M, int K, int PD, int XNT>
+__global__ __launch_bounds__(256, XNT == 128 ? 1 : 2) void stage_xres_bf16(const StageArgs a)
+{
+    constexpr int B = 16, NT = XNT, KT = 16;
+    using C = Bf16Cfg<M, B, K, 64, KT>;
+    constexpr int RS = C::RS, RSK = C::RSK, PART = C::PART, NV = C::NV;
+    constexpr int TM = 2, TN = NT / 32;     // wave w: rows 64 w .. 64 w + 63, all NT columns
+    constexpr bool B_IS_IN = K != 0;
+    constexpr int NQ = K + 1;               // insertion positions of the contracted mode
+    constexpr int XVT = NT * kXresMaxK / 8 / 256;   // X-slice vectors per thread (at most)
+    static_assert(C::G == 1 && C::VEC == 512 && NV == 2 && PART == 512, "one whole block part per chunk");
+    static_assert(C::DUAL || C::KM, "per-block regions or [row][kk]");
+    __shared__ XresSmem<M, K, XNT> sm;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int r32 = lane & 31, half = lane >> 5;
+    const int grp = lane >> 4, gl = lane & 15;
+    const u16 *in = (const u16 *)a.in;
+    const u16 *xp = (const u16 *)a.xp;
+    const int64_t *recw = (const int64_t *)a.xrec;
+    const int nbar = a.nbar;
+    const int nch_pad = (nbar + PD - 1) / PD * PD;
+    const int64_t Kx = a.Kx, Ppad = a.Ppad;
+    const int kvec = a.Kpad / 8;            // 16-byte vectors per X row
+    const int xv_count = NT * kvec;
+
+    // Digits of this thread's two vectors in the block part (fixed).
+    int vd0[NV], vd1[NV], vd2[NV];
+#pragma unroll
+    for (int f = 0; f < NV; ++f) {
+        const int w = tid + 256 * f;
+        vd0[f] = 8 * (w % (B / 8));
+        const int w1 = w / (B / 8);
+        vd1[f] = w1 % B;
+        vd2[f] = w1 / B;
+    }
+    // X-slice vector v = tid + 256 f: its row and k offset (fixed).
+    int xrow[XVT], xk[XVT];
+#pragma unroll
+    for (int f = 0; f < XVT; ++f) {
+        const int v = tid + 256 * f;
+        xrow[f] = v / kvec;
+        xk[f] = (v - xrow[f] * kvec) * 8;
+    }
+    // Per vector, its global and LDS offsets for insertion position q
+    // (16 bits each: goff < b^m <= 65536, loff < 2^13), packed in 64-bit
+    // words at bit 16 q: plain registers, selected with a uniform shift
+    // (arrays indexed per q would be placed in memory).
+    static_assert(M <= 4 && C::IN_ELEMS <= 65536, "offsets fit in 16 bits");
+    uint64_t gpk0 = 0, gpk1 = 0, lpk0 = 0, lpk1 = 0;
+    int cur_mt = -1;
+    int fixed[M > 3 ? M - 3 : 1] = {};
+
+    // Record words, loaded one task ahead: every thread loads word
+    // tid % words (so the load is not behind a branch), the first `words`
+    // threads store theirs.
+    const int rw = tid % kXresRecWords;
+    int64_t next_word = blockIdx.x < (unsigned)a.ntasks ? recw[(int64_t)blockIdx.x * kXresRecWords + rw] : 0;
+
+    for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
+        if (tid < kXresRecWords) sm.s_rec[tid] = next_word;
+        __syncthreads();
+        const int tn = t + gridDim.x;
+        next_word = recw[(int64_t)(tn < a.ntasks ? tn : t) * kXresRecWords + rw];
+        const XresRec *rec = (const XresRec *)sm.s_rec;
+        const int n0 = __builtin_amdgcn_readfirstlane(rec->n0);
+        const int mt = __builtin_amdgcn_readfirstlane(rec->mt);
+        const int Nvalid = __builtin_amdgcn_readfirstlane(rec->jcount) * B;
+        const uint32_t q_bits = __builtin_amdgcn_readfirstlane(rec->q_bits);
+
+        // X rows n0 .. n0 + 63 (zero past Ppad), k 0 .. Kpad - 1: every
+        // load first, then the stores.
+        u32x4 xr[XVT];
+#pragma unroll
+        for (int f = 0; f < XVT; ++f) {
+            const int64_t ng = n0 + xrow[f];
+            const bool ok = tid + 256 * f < xv_count && ng < Ppad;
+            xr[f] = *(const u32x4 *)(xp + (ok ? ng * Kx + xk[f] : 0));
+            if (!ok) xr[f] = u32x4{0u, 0u, 0u, 0u};
+        }
+        __builtin_amdgcn_sched_barrier(0);
+
+        if (mt != cur_mt) {
+            int r = mt;
+#pragma unroll
+            for (int j = 0; j < M - 3; ++j) {
+                fixed[j] = r % B;
+                r /= B;
+            }
+            auto offsets = [&](int f, uint64_t *gp, uint64_t *lp) {
+                uint64_t g = 0, l = 0;
+                bool ak = false;
+                int go = 0, lo = 0;
+#define STTSM_XQ(QQ) \
+    if constexpr (QQ < NQ) { \
+        place<M, B, K, QQ, RS, RSK, C::KM || QQ == 0>(vd0[f], vd1[f], vd2[f], fixed, 0, &go, &lo, &ak); \
+        g |= (uint64_t)(uint32_t)go << (16 * QQ); \
+        l |= (uint64_t)(uint32_t)lo << (16 * QQ); \
+    }
+                STTSM_XQ(0) STTSM_XQ(1) STTSM_XQ(2) STTSM_XQ(3)
+#undef STTSM_XQ
+                *gp = g;
+                *lp = l;
+            };
+            offsets(0, &gpk0, &lpk0);
+            offsets(1, &gpk1, &lpk1);
+            cur_mt = mt;
+        }
+
+        u32x4 rin[PD][NV];
+        int rl[PD][NV];
+        bool rv[PD], rq0[PD];
+        auto load_chunk = [&](int c, int u) {
+            const bool valid = c < nbar;
+            const int ib = valid ? c : 0;
+            const int q = (int)((q_bits >> (2 * ib)) & 3u);
+            const int64_t off = rec->off[ib];
+            const uint32_t olo = __builtin_amdgcn_readfirstlane((uint32_t)off);
+            const uint32_t ohi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)off >> 32));
+            const u16 *blk = in + (int64_t)(((uint64_t)ohi << 32) | olo);
+            rv[u] = valid;
+            rq0[u] = q == 0;
+            const uint32_t sh = 16u * (uint32_t)q;
+            const int go0 = (int)((gpk0 >> sh) & 0xFFFFu), go1 = (int)((gpk1 >> sh) & 0xFFFFu);
+            rl[u][0] = (int)((lpk0 >> sh) & 0xFFFFu);
+            rl[u][1] = (int)((lpk1 >> sh) & 0xFFFFu);
+            rin[u][0] = *(const u32x4 *)(blk + go0);
+            rin[u][1] = *(const u32x4 *)(blk + go1);
+        };
+        auto store_chunk = [&](int buf, int u) {
+            u16 *si = sm.s_in[buf];
+            const u32x4 zero = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int f = 0; f < NV; ++f) *(u32x4 *)&si[rl[u][f]] = rv[u] ? rin[u][f] : zero;
+        };
+
+        // The stages go out oldest first (see bf16_tile), after the X slice.
+#pragma unroll
+        for (int u = 0; u < PD; ++u) {
+            load_chunk(u, u);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int f = 0; f < XVT; ++f)
+            if (tid + 256 * f < xv_count) *(u32x4 *)&sm.s_x[xrow[f] * kXresXS + xk[f]] = xr[f];
+
+        f32x16 acc[TM][TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+        auto mfma_chunk = [&](int buf, int c, bool km) {
+            const u16 *si = sm.s_in[buf];
+            bf16x8 va[TM], vb[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const int rb = wave * 64 + 32 * i;
+                if (C::KM || km) {
+                    va[i] = __builtin_bit_cast(bf16x8, *(const u16x8 *)&si[(rb + r32) * RSK + 8 * half]);
+                } else {
+                    const int kk0 = 8 * (grp >> 1);
+                    const int rbase = rb + 16 * (grp & 1);
+                    const int o = (kk0 + (gl >> 2)) * RS + rbase + 4 * (gl & 3);
+                    typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+                    const s16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(si + o));
+                    const s16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4 *)(si + o + 4 * RS));
+                    va[i] = __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                vb[j] = __builtin_bit_cast(bf16x8, *(const u16x8 *)&sm.s_x[(32 * j + r32) * kXresXS + c * KT + 8 * half]);
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                if (j > 0 && n0 + 32 * j >= Nvalid) continue;   // no valid column in this subtile
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    if constexpr (B_IS_IN)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(vb[j], va[i], acc[i][j], 0, 0, 0);
+                    else
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[i], vb[j], acc[i][j], 0, 0, 0);
+                }
+            }
+        };
+
+        // Loads go out PD chunks ahead, unconditionally (chunks past nbar
+        // read block 0 and store zeros); the loop runs a multiple of PD
+        // chunks so that each store waits for its own register stage only.
+        // Chunks past nbar skip their MFMAs (the X slice holds nothing past
+        // Kpad).
+        for (int c0 = 0; c0 < nch_pad; c0 += PD) {
+#pragma unroll
+            for (int u = 0; u < PD; ++u) {
+                const int c = c0 + u;
+                store_chunk(c & 1, u);
+                const bool km = rq0[u];
+                __syncthreads();
+                load_chunk(c + PD, u);
+                if (c < nbar) mfma_chunk(c & 1, c, km);
+            }
+        }
+
+        // Epilogue (as in bf16_tile).
+        const int64_t out_base = rec->out_base, out_jstride = rec->out_jstride;
+        int64_t fixed_off = 0;
+#pragma unroll
+        for (int j = 0; j < M - 3; ++j) fixed_off += (int64_t)fixed[j] * a.mos[j + 2];
+        auto opart = [&](int mm) { return (int64_t)(mm % B) * a.mos[0] + (int64_t)(mm / B) * a.mos[1] + fixed_off; };
+        auto npart = [&](int ng) { return out_base + (int64_t)(ng / B) * out_jstride + (int64_t)(ng % B) * a.osk; };
+        if constexpr (K == 0) {
+            float *out = (float *)a.out;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int ng = n0 + j * 32 + r32;
+                if (ng < Nvalid) {
+                    float *oj = out + npart(ng);
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int mm = wave * 64 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                            oj[opart(mm)] = acc[i][j][r];
+                        }
+                }
+            }
+        } else {
+            __syncthreads();   // every wave is done with s_in, which s_out overlays
+            u16 *so = sm.s_out[wave];
+            u16 *out = (u16 *)a.out;
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+#pragma unroll
+                    for (int r = 0; r < 16; r += 2) {
+                        const uint32_t h = to_bf16x2(acc[i][j][r], acc[i][j][r + 1]);
+                        const int row = 8 * (r >> 2) + 4 * half + (r & 3);
+                        so[row * kOutRow + r32] = (u16)(h & 0xFFFFu);
+                        so[(row + 1) * kOutRow + r32] = (u16)(h >> 16);
+                    }
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int v = lane + 64 * h;
+                        const int col = v >> 2, run = (v & 3) * 8;
+                        const u32x4 w = *(const u32x4 *)&so[col * kOutRow + run];
+                        const int ng = n0 + j * 32 + col;
+                        const int mm = wave * 64 + i * 32 + run;
+                        if (ng < Nvalid) *(u32x4 *)(out + npart(ng) + opart(mm)) = w;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
+        }
+        __syncthreads();   // before the next task's record, X slice and staging
+    }
+}
+
 // Default tile (NT, KT, PD) per block size; the grouped kernel always uses it.
 template <int B>
 struct Bf16Default {
@@ -547,10 +853,79 @@ bool bf16_tile_supported(int b, int NT, int KT, int PD)
     return false;
 }
 
-int launch_stage_bf16(const StageArgs &a, int NT, int KT, int PD, hipStream_t s)
+bool bf16_xres_supported(int b, int Kpad, bool bf16_input)
+{
+    return b == 16 && Kpad >= 16 && Kpad <= kXresMaxK && bf16_input;
+}
+
+namespace {
+
+// Compute units of the current device (cached per device).
+int current_cus()
+{
+    static int cache[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cache[dev]) {
+        int c = 0;
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+        cache[dev] = c;
+    }
+    return cache[dev];
+}
+
+template <int M, int K>
+int launch_xres_k(const StageArgs &a, int NT, int PD, hipStream_t s)
+{
+    if (!a.xrec) return -1;
+    // resident workgroups per CU: two with 64- and 96-column tiles, one with 128
+    const int per_cu = NT == 128 ? 1 : 2;
+    const dim3 g((unsigned)std::max(1, std::min(a.ntasks, per_cu * current_cus()))), b(256);
+    if (NT == 64 && PD == 2) hipLaunchKernelGGL((stage_xres_bf16<M, K, 2, 64>), g, b, 0, s, a);
+    else if (NT == 64 && PD == 4) hipLaunchKernelGGL((stage_xres_bf16<M, K, 4, 64>), g, b, 0, s, a);
+    else if (NT == 96 && PD == 2) hipLaunchKernelGGL((stage_xres_bf16<M, K, 2, 96>), g, b, 0, s, a);
+    else if (NT == 96 && PD == 4) hipLaunchKernelGGL((stage_xres_bf16<M, K, 4, 96>), g, b, 0, s, a);
+    else if (NT == 128 && PD == 2) hipLaunchKernelGGL((stage_xres_bf16<M, K, 2, 128>), g, b, 0, s, a);
+    else if (NT == 128 && PD == 4) hipLaunchKernelGGL((stage_xres_bf16<M, K, 4, 128>), g, b, 0, s, a);
+    else return -1;
+    return 0;
+}
+
+int launch_xres(const StageArgs &a, int NT, int PD, hipStream_t s)
+{
+    if (a.m == 3) {
+        switch (a.k) {
+        case 0: return launch_xres_k<3, 0>(a, NT, PD, s);
+        case 1: return launch_xres_k<3, 1>(a, NT, PD, s);
+        case 2: return launch_xres_k<3, 2>(a, NT, PD, s);
+        default: return -1;
+        }
+    }
+    if (a.m == 4) {
+        switch (a.k) {
+        case 0: return launch_xres_k<4, 0>(a, NT, PD, s);
+        case 1: return launch_xres_k<4, 1>(a, NT, PD, s);
+        case 2: return launch_xres_k<4, 2>(a, NT, PD, s);
+        case 3: return launch_xres_k<4, 3>(a, NT, PD, s);
+        default: return -1;
+        }
+    }
+    return -1;
+}
+
+}  // namespace
+
+int launch_stage_bf16(const StageArgs &a, int NT, int KT, int PD, bool xres, hipStream_t s)
 {
     if (a.ntasks <= 0) return 0;
     if (!bf16_fast_supported(a.m, a.bA, a.bC, a.nbar)) return -1;
+    if (xres) {
+        if (!bf16_xres_supported(a.bA, a.Kpad, a.in_f32 == 0) || (NT != 64 && NT != 96 && NT != 128) || KT != 16)
+            return -1;
+        const int rc = launch_xres(a, NT, PD, s);
+        if (rc) return rc;
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+    }
     return launch_bf16_any(a.m, a.bA, a.k, a, NT, KT, PD, nullptr, nullptr, 0, nullptr, 0, s);
 }
 

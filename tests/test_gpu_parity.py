@@ -418,6 +418,10 @@ def bf16_fast_level0_tasks(m, n, p, b):
     import os
     nbar, pbar = -(-n // b), -(-p // b)
     nt = 64 if b == 16 else 128
+    # b = 16 with Kpad <= 256 on bf16 input: the X-resident form, 96-column tiles by default
+    xres = os.environ.get("STTSM_BF16_XRES", "")
+    if b == 16 and nbar * b <= 256 and not os.environ.get("STTSM_BF16_TILE") and xres != "0":
+        nt = int(xres.split("x")[0]) if "x" in xres else 96
     override = os.environ.get("STTSM_BF16_TILE", "")   # "NTxKTxPD", a measurement override
     if override and "," not in override:
         o_nt = int(override.split("x")[0])
@@ -485,6 +489,43 @@ def test_bf16_tile_variants(tiles, m, n, p, b, monkeypatch):
     assert e <= tol_bf16(m)
     check_entries(got, ref, S, PBF, -(-n // b) * b)
     assert np.all(got[padding_mask(m, p, b)] == 0.0)
+
+
+# The X-resident form of the bf16 block-copy kernel (b = 16, bf16 input,
+# Kpad <= 256) runs the same MFMA sequence on the same operands for every
+# output entry as the chunk-staged kernel, so both give the same C.
+XRES_SHAPES = [(3, 35, 35), (3, 100, 70), (3, 130, 60), (4, 40, 37), (4, 64, 64), (3, 256, 256), (3, 250, 17)]
+
+
+@pytest.mark.parametrize("m,n,p", XRES_SHAPES)
+def test_bf16_xres_matches_chunk_staged(m, n, p, monkeypatch):
+    import torch
+    b = 16
+    monkeypatch.delenv("STTSM_GENERIC_KERNELS", raising=False)
+    monkeypatch.delenv("STTSM_BF16_TILE", raising=False)
+    A = synth.round_to_bf16(synth.symmetric_uniform(m, n, (m, n, p, 97)))
+    X = synth.round_to_bf16(synth.change_of_basis(p, n, (m, n, p, 98)))
+    got = {}
+    modes = ("0", "64x2", "64x4", "96x2", "96x4", "128x2", "128x4")
+    for mode in modes:
+        monkeypatch.setenv("STTSM_BF16_XRES", mode)
+        for d in range(m):
+            info = st().sttsm_plan_info(m, n, p, b, b, PBF, d, dtype=st().BF16)
+            if mode == "0":
+                assert info["kernel"] == "bf16_block_copy"
+            else:
+                assert info["kernel"] == "bf16_xres"
+                assert (info["tile"][1], info["tile"][3]) == tuple(int(v) for v in mode.split("x"))
+        say("xres", mode, m, n, p)
+        got[mode] = run(A, X, b, b, PBF, dtype=torch.bfloat16)
+    for mode in modes[1:]:
+        assert np.array_equal(got["0"], got[mode]), mode
+    ref, S = reference(A, X, b)
+    e = err(got["96x2"], ref, m, p, b)
+    say("  rel err", e, "bound", tol_bf16(m))
+    assert e <= tol_bf16(m)
+    check_entries(got["96x2"], ref, S, PBF, -(-n // b) * b)
+    assert np.all(got["96x2"][padding_mask(m, p, b)] == 0.0)
 
 
 def test_bf16_block_copy_config2_full():
