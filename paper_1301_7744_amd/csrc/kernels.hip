@@ -88,6 +88,71 @@ __global__ void bcss_pack_kernel(const E *__restrict__ dense, E *__restrict__ bc
     }
 }
 
+// The vector case of bcss_pack_kernel (n and b multiples of 4, aligned
+// pointers): every run is either wholly inside the tensor or wholly padding,
+// since n - s_0 b is a multiple of 4.  Digits of a run's row are shifts when
+// b = 2^lb (lb >= 0).  Each thread takes kPackRuns runs at a time and issues
+// all their loads before any store.
+constexpr int kPackRuns = 4;
+
+template <class E>
+__global__ __launch_bounds__(256) void bcss_pack_vec_kernel(const E *__restrict__ dense, E *__restrict__ bcss, int m,
+                                                            int64_t n, int b, int lb, int64_t bm, int64_t nblocks,
+                                                            const int32_t *__restrict__ tuples, int rows, int runs)
+{
+    const int total = rows * runs;
+    for (int64_t r = blockIdx.x; r < nblocks; r += gridDim.x) {
+        int64_t base = 0, npow = 1;
+        int32_t sb[kMaxOrder];
+        for (int j = 0; j < m; ++j) {
+            sb[j] = tuples[r * m + j] * b;
+            base += (int64_t)sb[j] * npow;
+            npow *= n;
+        }
+        const int64_t lim0 = n - sb[0];
+        E *out = bcss + r * bm;
+        for (int t0 = threadIdx.x; t0 < total; t0 += kPackRuns * blockDim.x) {
+            Vec4<E> v[kPackRuns];
+#pragma unroll
+            for (int u = 0; u < kPackRuns; ++u) {
+                const int t = t0 + u * (int)blockDim.x;
+                v[u] = Vec4<E>{E(0), E(0), E(0), E(0)};
+                if (t >= total) continue;
+                int row, e0;
+                if (lb >= 0) {
+                    row = t >> (lb - 2);
+                    e0 = (t & (runs - 1)) * 4;
+                } else {
+                    row = t / runs;
+                    e0 = (t - row * runs) * 4;
+                }
+                int rr = row;
+                int64_t off = base, np = n;
+                bool ok = e0 < lim0;
+                for (int j = 1; j < m; ++j) {
+                    int lj;
+                    if (lb >= 0) {
+                        lj = rr & (b - 1);
+                        rr >>= lb;
+                    } else {
+                        lj = rr % b;
+                        rr /= b;
+                    }
+                    ok = ok && (int64_t)sb[j] + lj < n;
+                    off += (int64_t)lj * np;
+                    np *= n;
+                }
+                if (ok) v[u] = *(const Vec4<E> *)&dense[off + e0];
+            }
+#pragma unroll
+            for (int u = 0; u < kPackRuns; ++u) {
+                const int t = t0 + u * (int)blockDim.x;
+                if (t < total) *(Vec4<E> *)&out[(int64_t)t * 4] = v[u];
+            }
+        }
+    }
+}
+
 // Dense block t (dimensional order over nbar^m) <- stored block sort(t), read
 // through the permuted strides of the meta-data tensor (App. B).
 template <class E>
@@ -203,6 +268,99 @@ __global__ void bcss_unpack_lds_kernel(const E *__restrict__ bcss, E *__restrict
     }
 }
 
+// The vector case of bcss_unpack_lds_kernel (n and b multiples of 4,
+// aligned pointers).  The staged block sits in LDS at padded positions
+// pad(i) = i + i/16 + i/256, so that the permuted reads, whose strides along
+// a run are 1, b, b^2, ..., fall on distinct banks for b = 16 (strides 17
+// and 273 words); each thread takes kPackRuns runs at a time, reads all their
+// entries from LDS, then stores them; digits are shifts when b = 2^lb.
+__device__ __forceinline__ int unpack_pad(int i) { return i + (i >> 4) + (i >> 8); }
+
+template <class E>
+__global__ __launch_bounds__(256) void bcss_unpack_vec_kernel(const E *__restrict__ bcss, E *__restrict__ dense,
+                                                              int m, int64_t n, int b, int lb, int nbar, int bm,
+                                                              int64_t nbm, const int64_t *__restrict__ rank,
+                                                              const int32_t *__restrict__ perm,
+                                                              const int32_t *__restrict__ pstr, int rows, int runs,
+                                                              int src16)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char unpack_smem[];
+    E *sb = (E *)unpack_smem;
+    const bool vec16 = src16 && (bm * (int)sizeof(E)) % 16 == 0;
+    const int total = rows * runs;
+    for (int64_t tb = blockIdx.x; tb < nbm; tb += gridDim.x) {
+        int32_t tbj[kMaxOrder], ps[kMaxOrder];
+        int64_t base = 0, npow = 1, q = tb;
+        const int32_t *pp = pstr + (int64_t)perm[tb] * m;
+        for (int j = 0; j < m; ++j) {
+            tbj[j] = (int32_t)(q % nbar) * b;
+            q /= nbar;
+            base += (int64_t)tbj[j] * npow;
+            npow *= n;
+            ps[j] = pp[j];
+        }
+        const E *src = bcss + rank[tb] * (int64_t)bm;
+        const int64_t lim0 = n - tbj[0];
+        __syncthreads();   // the previous block's reads of the staging buffer are done
+        if (vec16 && sizeof(E) == 4) {
+            for (int v = threadIdx.x; v < bm / 4; v += blockDim.x) {
+                const uint4 w = ((const uint4 *)src)[v];
+                const int o = unpack_pad(4 * v);   // the four entries stay contiguous
+                uint32_t *d = (uint32_t *)sb + o;
+                d[0] = w.x;
+                d[1] = w.y;
+                d[2] = w.z;
+                d[3] = w.w;
+            }
+        } else {
+            for (int v = threadIdx.x; v < bm; v += blockDim.x) sb[unpack_pad(v)] = src[v];
+        }
+        __syncthreads();
+        for (int t0 = threadIdx.x; t0 < total; t0 += kPackRuns * blockDim.x) {
+            Vec4<E> v[kPackRuns];
+            int64_t dst[kPackRuns];
+            bool live[kPackRuns];
+#pragma unroll
+            for (int u = 0; u < kPackRuns; ++u) {
+                const int t = t0 + u * (int)blockDim.x;
+                int row, e0;
+                if (lb >= 0) {
+                    row = t >> (lb - 2);
+                    e0 = (t & (runs - 1)) * 4;
+                } else {
+                    row = t / runs;
+                    e0 = (t - row * runs) * 4;
+                }
+                int rr = row;
+                int64_t off = base, np = n;
+                int so = 0;
+                bool ok = t < total && e0 < lim0;
+                for (int j = 1; j < m; ++j) {
+                    int lj;
+                    if (lb >= 0) {
+                        lj = rr & (b - 1);
+                        rr >>= lb;
+                    } else {
+                        lj = rr % b;
+                        rr /= b;
+                    }
+                    ok = ok && (int64_t)tbj[j] + lj < n;
+                    off += (int64_t)lj * np;
+                    so += lj * ps[j];
+                    np *= n;
+                }
+                live[u] = ok;
+                dst[u] = off + e0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[u][e] = ok ? sb[unpack_pad(so + (e0 + e) * ps[0])] : E(0);
+            }
+#pragma unroll
+            for (int u = 0; u < kPackRuns; ++u)
+                if (live[u]) *(Vec4<E> *)&dense[dst[u]] = v[u];
+        }
+    }
+}
+
 template <class E>
 static int launch_pack_t(const void *dense, void *bcss, int m, int64_t n, int b, int64_t bm, int64_t nblocks,
                          const int32_t *tuples, hipStream_t s)
@@ -211,8 +369,15 @@ static int launch_pack_t(const void *dense, void *bcss, int m, int64_t n, int b,
     const int64_t grid = std::min<int64_t>(std::max<int64_t>(nblocks, 1), 1 << 16);
     const uintptr_t al = 4 * sizeof(E);
     const int vec = n % 4 == 0 && b % 4 == 0 && (uintptr_t)dense % al == 0 && (uintptr_t)bcss % al == 0;
-    hipLaunchKernelGGL(bcss_pack_kernel<E>, dim3((unsigned)grid), dim3(256), 0, s, (const E *)dense, (E *)bcss, m,
-                       n, b, bm, nblocks, tuples, rows, runs, vec);
+    int lb = -1;
+    for (int e = 2; e < 16; ++e)
+        if ((1 << e) == b) lb = e;
+    if (vec)
+        hipLaunchKernelGGL(bcss_pack_vec_kernel<E>, dim3((unsigned)grid), dim3(256), 0, s, (const E *)dense,
+                           (E *)bcss, m, n, b, lb, bm, nblocks, tuples, rows, runs);
+    else
+        hipLaunchKernelGGL(bcss_pack_kernel<E>, dim3((unsigned)grid), dim3(256), 0, s, (const E *)dense, (E *)bcss, m,
+                           n, b, bm, nblocks, tuples, rows, runs, vec);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -224,7 +389,15 @@ static int launch_unpack_t(const void *bcss, void *dense, int m, int64_t n, int 
     const int64_t grid = std::min<int64_t>(std::max<int64_t>(nbm, 1), 1 << 16);
     const uintptr_t al = 4 * sizeof(E);
     const int vec = n % 4 == 0 && b % 4 == 0 && (uintptr_t)dense % al == 0 && (uintptr_t)bcss % al == 0;
-    if (bm * (int64_t)sizeof(E) <= kUnpackLdsBytes)
+    int lb = -1;
+    for (int e = 2; e < 16; ++e)
+        if ((1 << e) == b) lb = e;
+    if (vec && bm * (int64_t)sizeof(E) <= kUnpackLdsBytes)
+        hipLaunchKernelGGL(bcss_unpack_vec_kernel<E>, dim3((unsigned)grid), dim3(256),
+                           (size_t)((bm + bm / 16 + bm / 256 + 1) * sizeof(E)), s, (const E *)bcss, (E *)dense, m, n,
+                           b, lb, nbar, (int)bm, nbm, rank, perm, pstr, rows, runs,
+                           (int)((uintptr_t)bcss % 16 == 0));
+    else if (bm * (int64_t)sizeof(E) <= kUnpackLdsBytes)
         hipLaunchKernelGGL(bcss_unpack_lds_kernel<E>, dim3((unsigned)grid), dim3(256), (size_t)(bm * sizeof(E)), s,
                            (const E *)bcss, (E *)dense, m, n, b, nbar, (int)bm, nbm, rank, perm, pstr, rows, runs, vec,
                            (int)((uintptr_t)bcss % 16 == 0));
