@@ -266,7 +266,8 @@ int sttsm_workspace_temp(const bcss_layout *A, const bcss_layout *C, int32_t pre
  * the symmetric modes, Figure 6 with §6.3), of workgroup tasks, and the flops
  * the level performs (its term of Table 2).  tile (5 entries, may be NULL):
  * the level's kernel (0 generic, 1 FP32 block-copy, 2 bf16 block-copy, 3 bf16
- * block-copy with the X panel resident in LDS), its
+ * block-copy with the X panel resident in LDS, 4 bf16 for m = 2 with 64 x 64
+ * blocks, tiles of four row groups), its
  * tile rows and columns, K chunk and prefetch depth.  Any output may be NULL.
  */
 int sttsm_plan_info(const bcss_layout *A, const bcss_layout *C, int32_t prec, int32_t level,

@@ -188,7 +188,7 @@ def sttsm_plan_info(m: int, n: int, p: int, bA: int, bC: int, prec: int, level: 
     tile = (ctypes.c_int32 * 5)()
     _check(load().sttsm_plan_info(ctypes.byref(layout(m, n, bA, dtype)), ctypes.byref(layout(m, p, bC)), prec,
                                   level, ctypes.byref(g), ctypes.byref(t), ctypes.byref(f), tile))
-    kernel = ("generic", "fp32_block_copy", "bf16_block_copy", "bf16_xres")[tile[0]]
+    kernel = ("generic", "fp32_block_copy", "bf16_block_copy", "bf16_xres", "bf16_b64")[tile[0]]
     return dict(groups=g.value, tasks=t.value, flops=f.value, kernel=kernel, tile=tuple(tile[1:]))
 
 

@@ -13,7 +13,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsttsm.so")
-SOURCES = ["kernels.hip", "stage_bf16.hip", "symmetrize.hip", "vectors.hip", "noalloc.hip", "plan.cpp", "api.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "stage_bf16.hip", "stage_b64.hip", "symmetrize.hip", "vectors.hip", "noalloc.hip", "plan.cpp", "api.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

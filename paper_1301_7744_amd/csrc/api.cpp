@@ -224,7 +224,8 @@ int bcss_symmetrize(const bcss_layout *L, void *bcss, void *stream)
     if (!T) return fail(STTSM_ENOMEM, why);
     const StabTable *S = stab_get(L->m, &why);
     if (!S) return fail(STTSM_ENOMEM, why);
-    if (launch_symmetrize(L->dtype, bcss, L->m, L->b, T->d_tuples, T->d_rep_blocks, (int64_t)T->rep_blocks.size(),
+    if (launch_symmetrize(L->dtype, bcss, L->m, L->b, T->d_tuples, T->d_rep_blocks, T->d_rep_masks,
+                          (int64_t)T->rep_blocks.size(),
                           S->d_start, S->d_perm, S->d_pinv, as_stream(stream)))
         return fail(STTSM_EHIP, std::string("symmetrize launch failed: ") + hipGetErrorString(hipGetLastError()));
     return STTSM_OK;
@@ -311,7 +312,7 @@ int sttsm_plan_info(const bcss_layout *A, const bcss_layout *C, int32_t prec, in
     if (tasks) *tasks = (int64_t)S.tasks.size();
     if (flops) *flops = S.flops;
     if (tile) {
-        tile[0] = S.fast_bf16 ? (S.tile.xres ? 3 : 2) : S.fast ? 1 : 0;
+        tile[0] = S.b64 ? 4 : S.fast_bf16 ? (S.tile.xres ? 3 : 2) : S.fast ? 1 : 0;
         tile[1] = S.tile.MT;
         tile[2] = S.tile.NT;
         tile[3] = S.tile.KT;
@@ -381,7 +382,8 @@ int launch_levels(const Plan *P, const bcss_layout *A, const void *A_dev, const 
         a.xp_lo = S.xp_lo_slot >= 0 ? slot_ptr[S.xp_lo_slot] : nullptr;
         const long slot = prof_slot(S.d);
         if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot], s);
-        const int lrc = S.fast_bf16 ? launch_stage_bf16(a, S.tile.NT, S.tile.KT, S.tile.PD, S.tile.xres, s)
+        const int lrc = S.b64         ? launch_stage_b64(a, S.tile.NT, s)
+                        : S.fast_bf16 ? launch_stage_bf16(a, S.tile.NT, S.tile.KT, S.tile.PD, S.tile.xres, s)
                         : S.fast  ? launch_stage_fast(a, S.tile.MT, S.tile.NT, S.tile.KT, S.tile.PD, S.d == 0, s)
                                   : launch_stage(a, S.compute, S.tile.MT, S.tile.NT, S.d == 0, s);
         if (lrc)

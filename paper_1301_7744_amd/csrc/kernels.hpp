@@ -31,13 +31,17 @@ bool bf16_fast_supported(int m, int bA, int bC, int nbar);
 void bf16_fast_tile(int b, int *MT, int *NT, int *KT, int *PD);   // the default tile
 bool bf16_tile_supported(int b, int NT, int KT, int PD);
 int launch_stage_bf16(const StageArgs &a, int NT, int KT, int PD, bool xres, hipStream_t s);
+// bf16 kernel for m = 2 with 64 x 64 blocks (stage_b64.hip): 256-row tiles of
+// four row groups, NT in {128, 192, 256} columns, eight waves.
+bool b64_bf16_supported(int m, int bA, int bC, int nbar, bool bf16_input);
+int launch_stage_b64(const StageArgs &a, int NT, hipStream_t s);
 // Whether the X-resident bf16 form applies: b = 16, Kpad <= 256, bf16 input.
 bool bf16_xres_supported(int b, int Kpad, bool bf16_input);
 int launch_grouped_bf16(int m, int b, int k, const StageArgs *d_stages, const GroupedTask *d_tasks, int ntasks,
                         int *d_head, int grid, hipStream_t s);
 // In-place symmetrisation of the blocks with repeated indices (symmetrize.hip).
 int launch_symmetrize(int dtype, void *bcss, int m, int b, const int32_t *d_tuples, const int32_t *d_blocks,
-                      int64_t nlist, const int32_t *d_stab_start, const uint8_t *d_stab_perm,
+                      const uint8_t *d_masks, int64_t nlist, const int32_t *d_stab_start, const uint8_t *d_stab_perm,
                       const int32_t *d_stab_pinv, hipStream_t s);
 // Batched vector products y_v = A x_v^(m-1), s_v = x_v . y_v (vectors.hip);
 // part holds nchunks * V * b floats.

@@ -496,6 +496,8 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err, int cus)
         S.tile = key.grouped ? TileCfg{kGroupedMT, kGroupedNT, 2, 2} : choose_tile(Mblk);
         S.fast = fast[d];
         S.fast_bf16 = fast16[d];
+        S.b64 = cmp[d] == CMP_BF16 && b64_bf16_supported(m, bA, bC, nbar, in_dt == BF16) && !key.generic_only &&
+                !key.grouped;
         if (S.fast_bf16) {
             int tmt, tnt, tkt, tpd;
             bf16_fast_tile(bA, &tmt, &tnt, &tkt, &tpd);
@@ -667,9 +669,39 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err, int cus)
                 S.fopart[row] = op;
             }
         }
+        if (S.b64) {
+            // Tiles of four consecutive row groups (their rows stacked) and
+            // NT columns up to the largest of their column counts.  NT: the
+            // fewest resident rounds times the tile width (ties: wider).
+            const int ng = (int)S.groups.size();
+            auto count = [&](int nt) {
+                int64_t c = 0;
+                for (int g = 0; g < ng; g += 4) {
+                    int jmax = 0;
+                    for (int i = g; i < std::min(ng, g + 4); ++i) jmax = std::max(jmax, S.groups[i].jcount);
+                    c += (jmax * bC + nt - 1) / nt;
+                }
+                return c;
+            };
+            int best = 256;
+            int64_t best_cost = INT64_MAX;
+            for (int nt : {256, 192, 128}) {
+                const int64_t cost = (count(nt) + cus - 1) / cus * nt;
+                if (cost < best_cost) best = nt, best_cost = cost;
+            }
+            S.tile = TileCfg{256, best, 4, 2, 64, 2};
+            for (int g = 0; g < ng; g += 4) {
+                const int cnt = std::min(4, ng - g);
+                int jmax = 0;
+                for (int i = g; i < g + cnt; ++i) jmax = std::max(jmax, S.groups[i].jcount);
+                const int N = jmax * bC;
+                for (int nt = 0; nt * best < N; ++nt)
+                    S.tasks.push_back(Task{g, (int16_t)cnt, (int16_t)nt, 0, (int16_t)std::min(best, N - nt * best)});
+            }
+        }
         // Tasks.
-        const int mtiles = (Mblk + S.tile.MT - 1) / S.tile.MT;
-        for (int32_t gi = 0; gi < (int32_t)S.groups.size(); ++gi) {
+        const int mtiles = S.b64 ? 0 : (Mblk + S.tile.MT - 1) / S.tile.MT;
+        for (int32_t gi = 0; gi < (int32_t)S.groups.size() && !S.b64; ++gi) {
             const int N = S.groups[gi].jcount * bC;
             const int ntiles = (N + S.tile.NT - 1) / S.tile.NT;
             for (int mt = 0; mt < mtiles; ++mt)
@@ -917,15 +949,17 @@ const MetaTable *meta_get(int m, int nbar, int b, std::string *err)
         T->perm[f] = ins.first->second;
     }
     const int64_t nblk = (int64_t)T->tuples.size() / m;
-    for (int64_t r = 0; r < nblk; ++r)
-        for (int j = 0; j + 1 < m; ++j)
-            if (T->tuples[r * m + j] == T->tuples[r * m + j + 1]) {
-                T->rep_blocks.push_back((int32_t)r);
-                break;
-            }
+    for (int64_t r = 0; r < nblk; ++r) {
+        int mask = 0;
+        for (int j = 0; j + 1 < m; ++j) mask |= (T->tuples[r * m + j] == T->tuples[r * m + j + 1] ? 1 : 0) << j;
+        if (mask) {
+            T->rep_blocks.push_back((int32_t)r);
+            T->rep_masks.push_back((uint8_t)mask);
+        }
+    }
     if (!upload(T->rank, &T->d_rank, err) || !upload(T->perm, &T->d_perm, err) ||
         !upload(T->perm_strides, &T->d_perm_strides, err) || !upload(T->tuples, &T->d_tuples, err) ||
-        !upload(T->rep_blocks, &T->d_rep_blocks, err))
+        !upload(T->rep_blocks, &T->d_rep_blocks, err) || !upload(T->rep_masks, &T->d_rep_masks, err))
         return nullptr;
     const MetaTable *out = T.get();
     g_meta.emplace(key, std::move(T));

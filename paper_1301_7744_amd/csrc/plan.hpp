@@ -33,6 +33,7 @@ struct StagePlan {
     int compute = CMP_FP32;
     bool fast = false;  // block-copy staging kernel (whole 256-row blocks, bA | 16)
     bool fast_bf16 = false;   // block-copy bf16 kernel (m in {3, 4}, bA = bC in {8, 16})
+    bool b64 = false;         // bf16 kernel for m = 2, bA = bC = 64 (tasks of four row groups)
     TileCfg tile{};
     StageArgs args{};   // everything but in/out/xp pointers
     std::vector<GroupDesc> groups;
@@ -154,8 +155,10 @@ struct MetaTable {
     std::vector<int32_t> perm_strides;
     std::vector<int32_t> tuples;     // sorted block tuples in colex order, m each
     std::vector<int32_t> rep_blocks; // colex ranks of the tuples with a repeated index
+    std::vector<uint8_t> rep_masks;  // their run masks (bit j: s_j == s_{j+1})
     int64_t *d_rank = nullptr;
     int32_t *d_rep_blocks = nullptr;
+    uint8_t *d_rep_masks = nullptr;
     int32_t *d_perm = nullptr;
     int32_t *d_perm_strides = nullptr;
     int32_t *d_tuples = nullptr;

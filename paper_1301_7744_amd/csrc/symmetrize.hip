@@ -89,28 +89,29 @@ __global__ void bcss_symmetrize_kernel(E *__restrict__ bcss, int m, int b, int64
 }
 
 // The same averages with the block staged in LDS (blocks of at most
-// kSymLdsBytes), computed by every entry for itself: entry l finds its orbit
-// representative (the smallest image of l), sums the representative's
-// images in stabiliser order (so every member of an orbit adds the same
-// values in the same order and gets the same bits as the representative in
-// the kernel above), and writes only itself.  The block is read with
-// coalesced 16-byte vectors (4-byte words when its size is not a multiple of
-// 16 bytes) and every thread writes its own entries: no lane waits on
-// another's orbit.  The image of l under permutation p is
-// sum_i d_i(l) * b^(p^-1(i)): shifts by p^-1(i) * log2(b) from a host table
-// when b is a power of two, else weights tabulated in LDS once per block.
-// Each thread takes four entries at a time so that a permutation's weights
-// serve four images, and four workgroups share a block (each writes a
-// quarter of it).
+// kSymLdsBytes), one workgroup per block, computed by every entry for
+// itself: entry l finds its orbit representative (the smallest image of l),
+// sums the representative's images in stabiliser order (so every member of
+// an orbit adds the same values in the same order and gets the same bits as
+// the representative in the kernel above), and writes only itself.  The
+// whole block is staged before any entry is written, and no other workgroup
+// touches the block, so every average is taken over the block's values as
+// they were.  The block is read with coalesced 16-byte vectors (4-byte words
+// when its size is not a multiple of 16 bytes).  The image of l under
+// permutation p is sum_i d_i(l) * b^(p^-1(i)): shifts by p^-1(i) * log2(b)
+// from a host table when b is a power of two, else weights tabulated in LDS
+// once per block.  The run mask of each listed block comes from a host list
+// (loaded beside the block's rank), so the only loads that wait on another
+// are the block itself and the stabiliser's tables.
 constexpr int kSymLdsBytes = 32768;
 constexpr int kSymMaxPerms = 720;   // |S_6|
-constexpr int kSymSplit = 4;        // workgroups per block
+constexpr int kSymThreads = 1024;
 
 template <class E>
-__global__ void bcss_symmetrize_lds_kernel(E *__restrict__ bcss, int m, int b, int lb, int bm,
-                                           const int32_t *__restrict__ blocks, int64_t nlist,
-                                           const int32_t *__restrict__ tuples, const int32_t *__restrict__ stab_start,
-                                           const uint8_t *__restrict__ stab_perm, const int32_t *__restrict__ stab_pinv)
+__global__ __launch_bounds__(kSymThreads) void bcss_symmetrize_lds_kernel(
+    E *__restrict__ bcss, int m, int b, int lb, int bm, const int32_t *__restrict__ blocks,
+    const uint8_t *__restrict__ masks, int64_t nlist, const int32_t *__restrict__ stab_start,
+    const uint8_t *__restrict__ stab_perm, const int32_t *__restrict__ stab_pinv)
 {
     using Acc = SymAcc<E>;
     using T = typename Acc::T;
@@ -119,29 +120,24 @@ __global__ void bcss_symmetrize_lds_kernel(E *__restrict__ bcss, int m, int b, i
     E *sb = (E *)sym_smem;
     const int bytes = bm * (int)sizeof(E);
     const bool vec16 = bytes % 16 == 0;
-    // Workgroup item x covers part x % kSymSplit of block x / kSymSplit: it
-    // stages the whole block and writes that part of its entries.
-    for (int64_t x = blockIdx.x; x < nlist * kSymSplit; x += gridDim.x) {
-        const int64_t r = blocks[x / kSymSplit];
-        const int part = (int)(x % kSymSplit);
-        const int lbeg = (int)((int64_t)bm * part / kSymSplit), lend = (int)((int64_t)bm * (part + 1) / kSymSplit);
-        int mask = 0;
-        for (int j = 0; j + 1 < m; ++j) mask |= (tuples[r * m + j] == tuples[r * m + j + 1] ? 1 : 0) << j;
-        if (mask == 0) continue;
-        const int p0 = stab_start[mask], p1 = stab_start[mask + 1];
-        const int np = p1 - p0;   // <= kSymMaxPerms (checked by the launcher)
-        for (int t = threadIdx.x; t < np * m; t += blockDim.x) {
-            const int pp = t / m, j = t - pp * m;   // position j holds mode perm[j]: weight b^j for that mode
-            int w = 1;
-            for (int e = 0; e < j; ++e) w *= b;
-            s_w[pp * kMaxOrder + stab_perm[(p0 + pp) * m + j]] = w;
-        }
+    for (int64_t x = blockIdx.x; x < nlist; x += gridDim.x) {
+        const int64_t r = blocks[x];
+        const int mask = masks[x];
         E *blk = bcss + r * (int64_t)bm;
         if (vec16) {
             for (int v = threadIdx.x; v < bytes / 16; v += blockDim.x) ((uint4 *)sym_smem)[v] = ((const uint4 *)blk)[v];
         } else {
             for (int v = threadIdx.x; v < bm; v += blockDim.x) sb[v] = blk[v];
         }
+        const int p0 = stab_start[mask], p1 = stab_start[mask + 1];
+        const int np = p1 - p0;   // <= kSymMaxPerms (checked by the launcher)
+        if (lb < 0)
+            for (int t = threadIdx.x; t < np * m; t += blockDim.x) {
+                const int pp = t / m, j = t - pp * m;   // position j holds mode perm[j]: weight b^j for that mode
+                int w = 1;
+                for (int e = 0; e < j; ++e) w *= b;
+                s_w[pp * kMaxOrder + stab_perm[(p0 + pp) * m + j]] = w;
+            }
         __syncthreads();
         auto digits = [&](int l, int *d) {
             if (lb >= 0) {   // b = 2^lb: digits are bit fields
@@ -181,12 +177,12 @@ __global__ void bcss_symmetrize_lds_kernel(E *__restrict__ bcss, int m, int b, i
         // Four entries per thread at a time, so that every permutation's
         // weights are fetched once for four images.
         constexpr int kE = 4;
-        for (int l0 = lbeg + threadIdx.x; l0 < lend; l0 += kE * blockDim.x) {
+        for (int l0 = threadIdx.x; l0 < bm; l0 += kE * blockDim.x) {
             int d[kE][kMaxOrder], rep[kE];
 #pragma unroll
             for (int e = 0; e < kE; ++e) {
                 rep[e] = l0 + e * (int)blockDim.x;   // identity is the stabiliser's first element
-                digits(rep[e] < lend ? rep[e] : lbeg, d[e]);
+                digits(rep[e] < bm ? rep[e] : 0, d[e]);
             }
             int w[kMaxOrder];
             for (int pp = 1; pp < np; ++pp) {
@@ -195,7 +191,7 @@ __global__ void bcss_symmetrize_lds_kernel(E *__restrict__ bcss, int m, int b, i
                 for (int e = 0; e < kE; ++e) rep[e] = min(rep[e], image(d[e], w));
             }
 #pragma unroll
-            for (int e = 0; e < kE; ++e) digits(rep[e] < bm ? rep[e] : 0, d[e]);   // rep < bm always
+            for (int e = 0; e < kE; ++e) digits(rep[e] < bm ? rep[e] : 0, d[e]);
             T sum[kE];
 #pragma unroll
             for (int e = 0; e < kE; ++e) sum[e] = 0;
@@ -207,7 +203,7 @@ __global__ void bcss_symmetrize_lds_kernel(E *__restrict__ bcss, int m, int b, i
 #pragma unroll
             for (int e = 0; e < kE; ++e) {
                 const int l = l0 + e * (int)blockDim.x;
-                if (l < lend) blk[l] = Acc::store(sum[e] / (T)np);
+                if (l < bm) blk[l] = Acc::store(sum[e] / (T)np);
             }
         }
         __syncthreads();   // the next block reuses the staging buffer and the weights
@@ -215,8 +211,9 @@ __global__ void bcss_symmetrize_lds_kernel(E *__restrict__ bcss, int m, int b, i
 }
 
 template <class E>
-int launch_sym_t(void *bcss, int m, int b, int64_t bm, const int32_t *blocks, int64_t nlist, const int32_t *tuples,
-                 const int32_t *stab_start, const uint8_t *stab_perm, const int32_t *stab_pinv, hipStream_t s)
+int launch_sym_t(void *bcss, int m, int b, int64_t bm, const int32_t *blocks, const uint8_t *masks, int64_t nlist,
+                 const int32_t *tuples, const int32_t *stab_start, const uint8_t *stab_perm, const int32_t *stab_pinv,
+                 hipStream_t s)
 {
     const int64_t grid = std::min<int64_t>(std::max<int64_t>(nlist, 1), 1 << 16);
     int lb = -1;
@@ -229,9 +226,8 @@ int launch_sym_t(void *bcss, int m, int b, int64_t bm, const int32_t *blocks, in
     int fact = 1;
     for (int j = 2; j <= m; ++j) fact *= j;
     if (bytes <= kSymLdsBytes && fact <= kSymMaxPerms && (aligned || bytes % 16 != 0))
-        hipLaunchKernelGGL(bcss_symmetrize_lds_kernel<E>, dim3((unsigned)std::min<int64_t>(grid * kSymSplit, 1 << 16)),
-                           dim3(256), (size_t)bytes, s, (E *)bcss, m,
-                           b, lb, (int)bm, blocks, nlist, tuples, stab_start, stab_perm, stab_pinv);
+        hipLaunchKernelGGL(bcss_symmetrize_lds_kernel<E>, dim3((unsigned)grid), dim3(kSymThreads), (size_t)bytes, s,
+                           (E *)bcss, m, b, lb, (int)bm, blocks, masks, nlist, stab_start, stab_perm, stab_pinv);
     else
         hipLaunchKernelGGL(bcss_symmetrize_kernel<E>, dim3((unsigned)grid), dim3(256), 0, s, (E *)bcss, m, b, bm, blocks,
                            nlist, tuples, stab_start, stab_perm);
@@ -241,7 +237,7 @@ int launch_sym_t(void *bcss, int m, int b, int64_t bm, const int32_t *blocks, in
 }  // namespace
 
 int launch_symmetrize(int dtype, void *bcss, int m, int b, const int32_t *d_tuples, const int32_t *d_blocks,
-                      int64_t nlist, const int32_t *d_stab_start, const uint8_t *d_stab_perm,
+                      const uint8_t *d_masks, int64_t nlist, const int32_t *d_stab_start, const uint8_t *d_stab_perm,
                       const int32_t *d_stab_pinv, hipStream_t s)
 {
     int64_t bm = 1;
@@ -249,13 +245,13 @@ int launch_symmetrize(int dtype, void *bcss, int m, int b, const int32_t *d_tupl
     if (bm > INT32_MAX) return -1;
     if (nlist <= 0) return 0;
     if (dtype == F32)
-        return launch_sym_t<float>(bcss, m, b, bm, d_blocks, nlist, d_tuples, d_stab_start, d_stab_perm,
+        return launch_sym_t<float>(bcss, m, b, bm, d_blocks, d_masks, nlist, d_tuples, d_stab_start, d_stab_perm,
                                      d_stab_pinv, s);
     if (dtype == BF16)
-        return launch_sym_t<uint16_t>(bcss, m, b, bm, d_blocks, nlist, d_tuples, d_stab_start, d_stab_perm,
+        return launch_sym_t<uint16_t>(bcss, m, b, bm, d_blocks, d_masks, nlist, d_tuples, d_stab_start, d_stab_perm,
                                         d_stab_pinv, s);
     if (dtype == F64)
-        return launch_sym_t<double>(bcss, m, b, bm, d_blocks, nlist, d_tuples, d_stab_start, d_stab_perm,
+        return launch_sym_t<double>(bcss, m, b, bm, d_blocks, d_masks, nlist, d_tuples, d_stab_start, d_stab_perm,
                                       d_stab_pinv, s);
     return -1;
 }

@@ -744,3 +744,37 @@ def test_rank_update_one_pass_is_the_chain(case, monkeypatch):
     assert torch.equal(C1, C2)
     assert torch.equal(C1, C2b)
     assert torch.equal(C3, C4)
+
+
+# ------------------------------------------------------------------ m = 2, 64 x 64 blocks, bf16
+B64_SHAPES = [(2, 64, 64), (2, 70, 65), (2, 200, 300), (2, 1000, 900), (2, 4096, 4096)]
+
+
+@pytest.mark.parametrize("m,n,p", B64_SHAPES)
+def test_bf16_b64_kernel(m, n, p):
+    """bf16 inputs and temporaries, bA = bC = 64, through the kernel that
+    stacks four row groups per tile (both levels, every tile width it picks):
+    the whole C within the bf16 bound of the oracle run on the same bf16
+    values and entry by entry, padding exactly zero; at n = p = 4096 also
+    256 entries against the literal sum (O3)."""
+    import torch
+    b = 64
+    for d in range(m):
+        info = st().sttsm_plan_info(m, n, p, b, b, PBF, d, dtype=st().BF16)
+        say("b64", (m, n, p), d, info)
+        assert info["kernel"] == "bf16_b64"
+    if n == 4096:
+        A, X = synth.make_config_inputs("m2_n4096_b64")
+    else:
+        A = synth.symmetric_uniform(m, n, (m, n, p, 151))
+        X = synth.change_of_basis(p, n, (m, n, p, 152))
+    A, X = synth.round_to_bf16(A), synth.round_to_bf16(X)
+    got = run(A, X, b, b, PBF, dtype=torch.bfloat16)
+    ref, S = reference(A, X, b)
+    e = err(got, ref, m, p, b)
+    say("  rel err", e, "bound", tol_bf16(m))
+    assert e <= tol_bf16(m)
+    check_entries(got, ref, S, PBF, -(-n // b) * b)
+    assert np.all(got[padding_mask(m, p, b)] == 0.0)
+    if n == 4096:
+        check_literal_entries({PBF: got}, A, X, b, ref, S, n)
