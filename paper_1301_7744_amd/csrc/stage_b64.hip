@@ -143,7 +143,7 @@ __global__ __launch_bounds__(512, 1) void stage_b64_bf16(const StageArgs a)
         if (!wave_on) return;
         const u16 *A = sm.a[buf][rg];
         const u16 *X = sm.x[buf];
-        const bool kf = sm.kfast[rg][c];
+        const bool kf = __builtin_amdgcn_readfirstlane(sm.kfast[rg][c]) != 0;   // uniform over the wave
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             bf16x8 va[2], vb[TN];
@@ -206,6 +206,34 @@ __global__ __launch_bounds__(512, 1) void stage_b64_bf16(const StageArgs a)
     if (!wave_on) return;
     const int64_t ob = gd.out_base, ojs = gd.out_jstride, osk = a.osk, mos0 = a.mos[0];
     const bool f32out = a.out_f32 != 0;
+    if (ROWS_LANE && !f32out) {
+        // bf16 output contiguous along the rows (mos[0] = 1): each 64 x 32
+        // subtile goes through LDS as [col][row] and out as 16-byte stores of
+        // 8 consecutive rows (the loop above ended on a barrier, so the
+        // staging buffers are free; every wave has a region of its own).
+        u16 *so = &sm.a[0][0][0] + wave * (32 * kStr);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            if (wcol0 + 32 * j >= Nvalid) continue;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    so[(8 * (r >> 2) + 4 * half + (r & 3)) * kStr + 32 * i + r32] = to_bf16(acc[i][j][r]);
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int v = lane + 64 * h;
+                const int col = v >> 3, rc = (v & 7) * 8;
+                const int ng = wcol0 + 32 * j + col;
+                const u32x4 w = *(const u32x4 *)&so[col * kStr + rc];
+                if (ng < Nvalid)
+                    *(u32x4 *)((u16 *)a.out + ob + (int64_t)(ng / kB) * ojs + (int64_t)(ng % kB) * osk + rc) = w;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
 #pragma unroll
