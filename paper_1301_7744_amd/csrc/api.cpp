@@ -179,6 +179,9 @@ size_t sttsm_vectors_workspace_bytes(const bcss_layout *A, int64_t V)
     const int nbar = (int)((A->n + A->b - 1) / A->b);
     const VecPlan *P = vec_plan_get(A->m, nbar, A->b, false, &why);
     if (!P) return 0;
+    if (P->block_major)   // partials per entry, then per-block shares of the dot products
+        return ((P->entries.size() * (size_t)V * (size_t)A->b * sizeof(float) + 255) / 256 * 256) +
+               (size_t)nbar * (size_t)V * sizeof(float);
     return std::max<size_t>(256, (size_t)P->chunk_u.size() * (size_t)V * (size_t)A->b * sizeof(float));
 }
 
@@ -206,8 +209,17 @@ int sttsm_vectors(const bcss_layout *A, const void *A_dev, const void *x_dev, in
     const VecPlan *P = vec_plan_get(A->m, nbar, A->b, true, &why);
     if (!P) return fail(STTSM_ENOMEM, why);
     if (ws_bytes < sttsm_vectors_workspace_bytes(A, V)) return fail(STTSM_EINVAL, "workspace too small");
-    if (launch_vectors(A->dtype, A_dev, x_dev, rs_x, V, A->m, A->n, A->b, P->d_entries, P->d_chunk_begin,
-                       P->d_u_chunk, (int)P->chunk_u.size(), (float *)ws, y_dev, rs_y, s_dev, as_stream(stream)))
+    const int lrc =
+        P->block_major
+            ? launch_vectors_blocks(A->dtype, A_dev, x_dev, rs_x, V, A->n, A->b, (int64_t)P->blk_begin.size() - 1,
+                                    P->d_entries, P->d_blk_begin, P->d_blk_terms, P->d_u_entry, (float *)ws,
+                                    (float *)((char *)ws + (P->entries.size() * (size_t)V * (size_t)A->b *
+                                                                sizeof(float) + 255) / 256 * 256),
+                                    y_dev, rs_y, s_dev, as_stream(stream))
+            : launch_vectors(A->dtype, A_dev, x_dev, rs_x, V, A->m, A->n, A->b, P->d_entries, P->d_chunk_begin,
+                             P->d_u_chunk, (int)P->chunk_u.size(), (float *)ws, y_dev, rs_y, s_dev,
+                             as_stream(stream));
+    if (lrc)
         return fail(STTSM_EHIP, std::string("vector launch failed: ") + hipGetErrorString(hipGetLastError()));
     return STTSM_OK;
 }

@@ -48,6 +48,12 @@ int launch_symmetrize(int dtype, void *bcss, int m, int b, const int32_t *d_tupl
 int launch_vectors(int dtype, const void *A, const void *x, int64_t rs_x, int64_t V, int m, int64_t n, int b,
                    const VecEntry *d_entries, const int32_t *d_chunk_begin, const int32_t *d_u_chunk, int nchunks,
                    float *part, float *y, int64_t rs_y, float *s, hipStream_t st);
+// Block-major form for m = 3, b in {4, 8, 16}: one workgroup per stored
+// block (nblocks); part holds nentries * V * b floats, dotp nbar * V.
+int launch_vectors_blocks(int dtype, const void *A, const void *x, int64_t rs_x, int64_t V, int64_t n, int b,
+                          int64_t nblocks, const VecEntry *d_entries, const int32_t *d_blk_begin,
+                          const int32_t *d_blk_terms, const int32_t *d_u_entry, float *part, float *dotp, float *y,
+                          int64_t rs_y, float *s, hipStream_t st);
 int launch_prep_xt(int esize, const void *X, int64_t rs, int64_t cs, int64_t p, int64_t n, int64_t Kt, int64_t Pt,
                    float *xt, hipStream_t s);
 

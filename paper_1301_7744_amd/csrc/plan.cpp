@@ -1237,8 +1237,22 @@ const VecPlan *vec_plan_get(int m, int nbar, int b, bool upload, std::string *er
         P->u_chunk.push_back((int32_t)P->chunk_u.size());
     }
     P->chunk_begin.push_back((int32_t)P->entries.size());
+    P->block_major = m == 3 && (b == 4 || b == 8 || b == 16);
+    if (P->block_major) {
+        P->u_entry.push_back(0);
+        for (int u = 0; u < nbar; ++u) P->u_entry.push_back(P->u_entry.back() + (int32_t)per_u[u].size());
+        std::vector<std::vector<int32_t>> per_r(nblocks);
+        for (size_t e = 0; e < P->entries.size(); ++e) per_r[P->entries[e].r].push_back((int32_t)e);
+        P->blk_begin.push_back(0);
+        for (int64_t r = 0; r < nblocks; ++r) {
+            P->blk_terms.insert(P->blk_terms.end(), per_r[r].begin(), per_r[r].end());
+            P->blk_begin.push_back((int32_t)P->blk_terms.size());
+        }
+    }
     if (upload && (!upload_vec(P->entries, &P->d_entries, err) || !upload_vec(P->chunk_begin, &P->d_chunk_begin, err) ||
-                   !upload_vec(P->chunk_u, &P->d_chunk_u, err) || !upload_vec(P->u_chunk, &P->d_u_chunk, err)))
+                   !upload_vec(P->chunk_u, &P->d_chunk_u, err) || !upload_vec(P->u_chunk, &P->d_u_chunk, err) ||
+                   !upload_vec(P->blk_begin, &P->d_blk_begin, err) || !upload_vec(P->blk_terms, &P->d_blk_terms, err) ||
+                   !upload_vec(P->u_entry, &P->d_u_entry, err)))
         return nullptr;
     const VecPlan *out = P.get();
     g_vec.emplace(key, std::move(P));

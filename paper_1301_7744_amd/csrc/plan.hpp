@@ -185,6 +185,14 @@ struct VecPlan {
     int64_t terms = 0;                  // sum over entries of b^m (multiply-adds per vector)
     VecEntry *d_entries = nullptr;
     int32_t *d_chunk_begin = nullptr, *d_chunk_u = nullptr, *d_u_chunk = nullptr;
+    // Block-major form (m = 3, b in {4, 8, 16}): one workgroup per stored
+    // block serves every vector and every term of the block, so A is read
+    // once per batch.  Block r's terms are entries blk_terms[blk_begin[r] ..
+    // blk_begin[r + 1]); output block row u sums entries u_entry[u] ..
+    // u_entry[u + 1] (entries are grouped by u), one partial per entry.
+    bool block_major = false;
+    std::vector<int32_t> blk_begin, blk_terms, u_entry;
+    int32_t *d_blk_begin = nullptr, *d_blk_terms = nullptr, *d_u_entry = nullptr;
 };
 // Built on the host (and uploaded when upload is true), cached per device.
 const VecPlan *vec_plan_get(int m, int nbar, int b, bool upload, std::string *err);

@@ -8,7 +8,9 @@
 // block tuples with that leading index that sort to the block (VecEntry).
 // Deterministic: the first kernel writes one partial per (chunk of terms,
 // vector, row), the second adds each row's chunks in a fixed order and forms
-// the dot products with a fixed reduction tree.  No atomics.
+// the dot products with a fixed reduction tree.  No atomics.  For m = 3 the
+// first kernel is block-major instead (vec_block3_kernel: every stored block
+// read once per batch, one partial per term).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -143,6 +145,92 @@ __global__ __launch_bounds__(256) void vec_reduce_kernel(const float *__restrict
     if (threadIdx.x == 0 && s) s[v] = red[0];
 }
 
+// Block-major form for m = 3: one workgroup per stored block (entry
+// (d0, d1, d2) at stored digits d, block tuple s0 <= s1 <= s2), which it reads
+// once into LDS and then contracts with every vector of the batch, VB = 256/B
+// vectors per pass.  Thread (vl, d2) runs over the block's (d0, d1) plane at
+// its d2:
+//   g1[d1]  = sum_d0 a x0[d0]           (no x2: gives position 2 and, times
+//   T2[d2]  = sum_d1 x1[d1] g1[d1]       x2, position 1's partial)
+//   T0[d0]  = x2 sum_d1 a x1[d1]        (partial over d2)
+//   T1[d1]  = x2 g1[d1]                 (partial over d2)
+// with x_j the vector's segment at block index s_j.  The partials over d2 are
+// added through LDS in a fixed order (d2 = 0, 1, ...).  Each of the block's
+// terms (the first position q of each distinct index, weight w) writes
+// w T_q to its own partial slot; the rows of y add their slots in order.
+template <class E, int B>
+__global__ __launch_bounds__(256) void vec_block3_kernel(const E *__restrict__ A, const E *__restrict__ x,
+                                                         int64_t rs_x, int64_t V, int64_t n,
+                                                         const VecEntry *__restrict__ entries,
+                                                         const int32_t *__restrict__ blk_begin,
+                                                         const int32_t *__restrict__ blk_terms,
+                                                         float *__restrict__ part)
+{
+    constexpr int VB = 256 / B;
+    constexpr int S2 = B * B + 1;   // LDS stride of digit 2 (spreads the d2 threads over banks)
+    __shared__ float s_blk[B * S2];
+    __shared__ float s_x[3][VB][B];
+    __shared__ float s_red[2][VB][B][B + 1];
+    const int64_t r = blockIdx.x;
+    const int tid = threadIdx.x, vl = tid / B, d2 = tid % B;
+    const int t0 = blk_begin[r], t1 = blk_begin[r + 1];
+    const VecEntry e0 = entries[blk_terms[t0]];
+    const int64_t seg[3] = {(int64_t)e0.s[0] * B, (int64_t)e0.s[1] * B, (int64_t)e0.s[2] * B};
+    const E *blk = A + r * (B * B * B);
+    for (int g = tid; g < B * B * B; g += 256) s_blk[(g % (B * B)) + (g / (B * B)) * S2] = ld(blk, g);
+    for (int64_t v0 = 0; v0 < V; v0 += VB) {
+        const int64_t v = v0 + vl;
+        const bool live = v < V;
+        __syncthreads();   // the block is staged; the previous pass is done with s_x and s_red
+        for (int t = tid; t < 3 * VB * B; t += 256) {
+            const int j = t / (VB * B), vv = (t / B) % VB, d = t % B;
+            const int64_t xi = seg[j] + d, xv = v0 + vv;
+            s_x[j][vv][d] = (xv < V && xi < n) ? ld(x, xv * rs_x + xi) : 0.f;
+        }
+        __syncthreads();
+        float x0[B], x1[B], T0[B], g1[B];
+#pragma unroll
+        for (int d = 0; d < B; ++d) {
+            x0[d] = s_x[0][vl][d];
+            x1[d] = s_x[1][vl][d];
+            T0[d] = 0.f;
+            g1[d] = 0.f;
+        }
+        const float x2 = s_x[2][vl][d2];
+        const float *ab = s_blk + d2 * S2;
+#pragma unroll
+        for (int d1 = 0; d1 < B; ++d1)
+#pragma unroll
+            for (int d0 = 0; d0 < B; ++d0) {
+                const float av = ab[d0 + B * d1];
+                g1[d1] += av * x0[d0];
+                T0[d0] += av * x1[d1];
+            }
+        float T2 = 0.f;
+#pragma unroll
+        for (int d1 = 0; d1 < B; ++d1) T2 += x1[d1] * g1[d1];
+#pragma unroll
+        for (int d = 0; d < B; ++d) {
+            s_red[0][vl][d2][d] = x2 * T0[d];
+            s_red[1][vl][d2][d] = x2 * g1[d];
+        }
+        __syncthreads();
+        float R0 = 0.f, R1 = 0.f;   // rows l = d2 of positions 0 and 1, added over the d2 slices in order
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            R0 += s_red[0][vl][k][d2];
+            R1 += s_red[1][vl][k][d2];
+        }
+        if (live)
+            for (int t = t0; t < t1; ++t) {
+                const int idx = blk_terms[t];
+                const int q = entries[idx].q;
+                const float val = q == 0 ? R0 : (q == 1 ? R1 : T2);
+                part[((int64_t)idx * V + v) * B + d2] = entries[idx].w * val;
+            }
+    }
+}
+
 template <class E>
 int launch_vec_t(const void *A, const void *x, int64_t rs_x, int64_t V, int m, int64_t n, int b,
                  const VecEntry *d_entries, const int32_t *d_chunk_begin, const int32_t *d_u_chunk, int nchunks,
@@ -166,7 +254,110 @@ int launch_vec_t(const void *A, const void *x, int64_t rs_x, int64_t V, int m, i
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Rows of y for the block-major form: workgroup (v, u) adds, for each of
+// the b rows of output block u, the partials of u's entries, S = 256 / b
+// slices of the entry list per row (slice k takes entries k, k + S, ...,
+// each in order) joined by a fixed pairwise tree; it writes the rows and the
+// block's share of x_v . y_v (its b products added in order).
+template <class E>
+__global__ __launch_bounds__(256) void vec_rows_kernel(const float *__restrict__ part,
+                                                       const int32_t *__restrict__ u_entry,
+                                                       const E *__restrict__ x, int64_t rs_x, int64_t V, int64_t n,
+                                                       int b, float *__restrict__ y, int64_t rs_y,
+                                                       float *__restrict__ dotp)
+{
+    __shared__ float red[256];
+    const int64_t v = blockIdx.x;
+    const int u = blockIdx.y;
+    const int S = 256 / b;
+    const int l = threadIdx.x % b, k = threadIdx.x / b;
+    float acc = 0.f;
+    if (k < S)
+        for (int c = u_entry[u] + k; c < u_entry[u + 1]; c += S) acc += part[((int64_t)c * V + v) * b + l];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = S / 2; h > 0; h >>= 1) {
+        if (k < h) red[threadIdx.x] += red[threadIdx.x + h * b];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        float dot = 0.f;
+        for (int i = 0; i < b; ++i) {
+            const int64_t row = (int64_t)u * b + i;
+            if (row < n) {
+                y[v * rs_y + row] = red[i];
+                dot += ld(x, v * rs_x + row) * red[i];
+            }
+        }
+        dotp[(int64_t)u * V + v] = dot;
+    }
+}
+
+// s_v: the blocks' shares of x_v . y_v added in block order.
+__global__ __launch_bounds__(256) void vec_dot_kernel(const float *__restrict__ dotp, int nbar, int64_t V,
+                                                      float *__restrict__ s)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    float t = 0.f;
+    for (int u = 0; u < nbar; ++u) t += dotp[(int64_t)u * V + v];
+    s[v] = t;
+}
+
+template <class E, int B>
+int launch_vec_blocks_b(const void *A, const void *x, int64_t rs_x, int64_t V, int64_t n, int64_t nblocks,
+                        const VecEntry *d_entries, const int32_t *d_blk_begin, const int32_t *d_blk_terms,
+                        const int32_t *d_u_entry, float *part, float *dotp, float *y, int64_t rs_y, float *s,
+                        hipStream_t st)
+{
+    const int64_t nbar = (n + B - 1) / B;
+    if (nblocks > INT32_MAX || V > INT32_MAX || nbar > 65535) return -1;
+    hipLaunchKernelGGL((vec_block3_kernel<E, B>), dim3((unsigned)nblocks), dim3(256), 0, st, (const E *)A,
+                       (const E *)x, rs_x, V, n, d_entries, d_blk_begin, d_blk_terms, part);
+    hipLaunchKernelGGL(vec_rows_kernel<E>, dim3((unsigned)V, (unsigned)nbar), dim3(256), 0, st, (const float *)part,
+                       d_u_entry, (const E *)x, rs_x, V, n, B, y, rs_y, dotp);
+    if (s)
+        hipLaunchKernelGGL(vec_dot_kernel, dim3((unsigned)((V + 255) / 256)), dim3(256), 0, st, (const float *)dotp,
+                           (int)nbar, V, s);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <class E>
+int launch_vec_blocks_t(const void *A, const void *x, int64_t rs_x, int64_t V, int64_t n, int b, int64_t nblocks,
+                        const VecEntry *d_entries, const int32_t *d_blk_begin, const int32_t *d_blk_terms,
+                        const int32_t *d_u_entry, float *part, float *dotp, float *y, int64_t rs_y, float *s,
+                        hipStream_t st)
+{
+    switch (b) {
+    case 4:
+        return launch_vec_blocks_b<E, 4>(A, x, rs_x, V, n, nblocks, d_entries, d_blk_begin, d_blk_terms, d_u_entry,
+                                         part, dotp, y, rs_y, s, st);
+    case 8:
+        return launch_vec_blocks_b<E, 8>(A, x, rs_x, V, n, nblocks, d_entries, d_blk_begin, d_blk_terms, d_u_entry,
+                                         part, dotp, y, rs_y, s, st);
+    case 16:
+        return launch_vec_blocks_b<E, 16>(A, x, rs_x, V, n, nblocks, d_entries, d_blk_begin, d_blk_terms, d_u_entry,
+                                          part, dotp, y, rs_y, s, st);
+    default: return -1;
+    }
+}
+
 }  // namespace
+
+int launch_vectors_blocks(int dtype, const void *A, const void *x, int64_t rs_x, int64_t V, int64_t n, int b,
+                          int64_t nblocks, const VecEntry *d_entries, const int32_t *d_blk_begin,
+                          const int32_t *d_blk_terms, const int32_t *d_u_entry, float *part, float *dotp, float *y,
+                          int64_t rs_y, float *s, hipStream_t st)
+{
+    if (V <= 0 || nblocks <= 0) return V <= 0 ? 0 : -1;
+    if (dtype == F32)
+        return launch_vec_blocks_t<float>(A, x, rs_x, V, n, b, nblocks, d_entries, d_blk_begin, d_blk_terms,
+                                          d_u_entry, part, dotp, y, rs_y, s, st);
+    if (dtype == BF16)
+        return launch_vec_blocks_t<uint16_t>(A, x, rs_x, V, n, b, nblocks, d_entries, d_blk_begin, d_blk_terms,
+                                             d_u_entry, part, dotp, y, rs_y, s, st);
+    return -1;
+}
 
 int launch_vectors(int dtype, const void *A, const void *x, int64_t rs_x, int64_t V, int m, int64_t n, int b,
                    const VecEntry *d_entries, const int32_t *d_chunk_begin, const int32_t *d_u_chunk, int nchunks,

@@ -648,7 +648,8 @@ def test_symmetrize_after_sttsm():
 # ------------------------------------------------------------------ vector case
 @pytest.mark.parametrize("m,n,b,V,dt", [(2, 33, 8, 4, "f32"), (3, 16, 4, 5, "f32"), (3, 35, 16, 7, "f32"),
                                         (4, 9, 2, 3, "f32"), (5, 7, 3, 6, "f32"), (3, 256, 16, 64, "f32"),
-                                        (3, 40, 8, 9, "bf16")])
+                                        (3, 40, 8, 9, "bf16"), (3, 30, 4, 70, "f32"), (3, 21, 8, 40, "f32"),
+                                        (3, 100, 16, 17, "bf16")])
 def test_vectors_vs_oracle(m, n, b, V, dt):
     """y_v = A x_v^(m-1), s_v = A x_v^m on the GPU against the oracle (FP64
     mode products) on the same values; repeated calls give identical bits."""
