@@ -775,14 +775,19 @@ def main():
             ref_fn(A64, X64)
             t_cpu += time.perf_counter() - t
             runs += 1
+            log("bench: CPU oracle run %d: %.2f s" % (runs, time.perf_counter() - t))
         cpu_gflops = flops / (t_cpu / runs) / 1e9
-        # one thread, one run; and the literal sum (O1) on the small
-        # configuration m3_n16_b4, all threads
-        oracle.set_num_threads(1)
-        t = time.perf_counter()
-        ref_fn(A64, X64)
-        t_one = time.perf_counter() - t
-        oracle.set_num_threads(threads)
+        # one thread, one run when that is expected to take under a minute
+        # (else null); and the literal sum (O1) on the small configuration
+        # m3_n16_b4, all threads
+        t_one = None
+        if t_cpu / runs * threads <= 60.0:
+            log("bench: CPU oracle, one thread")
+            oracle.set_num_threads(1)
+            t = time.perf_counter()
+            ref_fn(A64, X64)
+            t_one = time.perf_counter() - t
+            oracle.set_num_threads(threads)
         A1, X1 = synth.make_config_inputs("m3_n16_b4")
         t = time.perf_counter()
         oracle.direct_sum(A1.astype(np.float64), X1.astype(np.float64))
@@ -793,8 +798,9 @@ def main():
             "sample": "full workload, dense FP64 mode-product chain (%.1f GFLOP of dense work per run; the "
                       "value divides Table 2's count by its time), %d run(s), %.1f s" % (dense_flops / 1e9, runs,
                                                                                         t_cpu),
-            "cpu_model": cpu_model(), "one_thread_gflops": round(flops / t_one / 1e9, 3),
-            "one_thread_s": round(t_one, 2),
+            "cpu_model": cpu_model(),
+            "one_thread_gflops": round(flops / t_one / 1e9, 3) if t_one else None,
+            "one_thread_s": round(t_one, 2) if t_one else None,
             "o1_direct_sum_m3_n16_b4_s": round(t_o1, 4)}
     if other is not None:
         out["bf16"] = other

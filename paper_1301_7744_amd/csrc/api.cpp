@@ -368,13 +368,22 @@ int launch_levels(const Plan *P, const bcss_layout *A, const void *A_dev, const 
     float *x32 = P->xp_off[0] >= 0 ? (float *)(w + P->xp_off[0]) : nullptr;
     uint16_t *xhi = P->xp_off[1] >= 0 ? (uint16_t *)(w + P->xp_off[1]) : nullptr;
     uint16_t *xlo = P->xp_off[2] >= 0 ? (uint16_t *)(w + P->xp_off[2]) : nullptr;
+    // A bf16 X that already has the bf16 panel's layout (rows of exactly Kx
+    // = n entries, 16-byte aligned, no padding rows or columns) is read in
+    // place: the panel would be a copy of it, entry for entry.
+    const uint16_t *xhi_read = xhi;
+    if (xhi && A->dtype == STTSM_BF16 && cs_x == 1 && rs_x == P->Kx && P->n == P->Kx && P->p == P->Ppad &&
+        ((uintptr_t)X_dev & 15) == 0) {
+        xhi_read = (const uint16_t *)X_dev;
+        xhi = nullptr;
+    }
     if ((x32 || xhi || xlo) &&
         launch_prep_x(dtype_size(A->dtype), X_dev, rs_x, cs_x, P->p, P->n, P->Ppad, P->Kx, x32, xhi, xlo, s))
         return fail(STTSM_EHIP, std::string("X panel launch failed: ") + hipGetErrorString(hipGetLastError()));
     float *xt = P->xp_off[3] >= 0 ? (float *)(w + P->xp_off[3]) : nullptr;
     if (xt && launch_prep_xt(dtype_size(A->dtype), X_dev, rs_x, cs_x, P->p, P->n, P->Kt, P->Pt, xt, s))
         return fail(STTSM_EHIP, std::string("X panel launch failed: ") + hipGetErrorString(hipGetLastError()));
-    const void *slot_ptr[4] = {x32, xhi, xlo, xt};
+    const void *slot_ptr[4] = {x32, xhi_read, xlo, xt};
     for (int d = 0; d <= last; ++d) {
         const StagePlan &S = P->stages[d];
         StageArgs a = S.args;

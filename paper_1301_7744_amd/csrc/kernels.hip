@@ -529,24 +529,59 @@ __global__ void prep_xt_kernel(const E *__restrict__ X, int64_t rs, int64_t cs, 
     if (i < Kt && j < Pt) xt[i * Pt + j] = t[c][r];
 }
 
+// Eight consecutive entries of a panel row per thread (Kx is a multiple of
+// 8): one row index division per eight entries, 16-byte stores of every
+// panel, and 16-byte loads of X where its row is contiguous and aligned.
 template <class E>
 __global__ void prep_x_kernel(const E *__restrict__ X, int64_t rs, int64_t cs, int64_t p, int64_t n,
                               int64_t Ppad, int64_t Kx, float *__restrict__ x32, u16 *__restrict__ xhi,
                               u16 *__restrict__ xlo)
 {
-    const int64_t total = Ppad * Kx;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t j = e / Kx, i = e - j * Kx;
-        float v = 0.f;
-        if (j < p && i < n) {
-            if constexpr (sizeof(E) == 4) v = __uint_as_float(X[j * rs + i * cs]);
-            else v = bf2f(X[j * rs + i * cs]);
+    const int64_t total8 = Ppad * Kx / 8;
+    for (int64_t e8 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e8 < total8;
+         e8 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = e8 * 8, j = e / Kx, i0 = e - j * Kx;
+        float v[8];
+        const E *src = X + j * rs + i0 * cs;
+        if (j < p && i0 + 8 <= n && cs == 1 && ((uintptr_t)src & 15) == 0) {
+            if constexpr (sizeof(E) == 4) {
+                const float4 a = *(const float4 *)src, b = *(const float4 *)(src + 4);
+                v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+            } else {
+                const uint4 w = *(const uint4 *)src;
+                const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    v[2 * q] = bf2f((u16)(ww[q] & 0xFFFFu));
+                    v[2 * q + 1] = bf2f((u16)(ww[q] >> 16));
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int64_t i = i0 + q;
+                v[q] = 0.f;
+                if (j < p && i < n) {
+                    if constexpr (sizeof(E) == 4) v[q] = __uint_as_float(X[j * rs + i * cs]);
+                    else v[q] = bf2f(X[j * rs + i * cs]);
+                }
+            }
         }
-        if (x32) x32[e] = v;
-        const u16 h = f2bf(v);
-        if (xhi) xhi[e] = h;
-        if (xlo) xlo[e] = f2bf(v - bf2f(h));
+        if (x32) {
+            *(float4 *)(x32 + e) = float4{v[0], v[1], v[2], v[3]};
+            *(float4 *)(x32 + e + 4) = float4{v[4], v[5], v[6], v[7]};
+        }
+        if (xhi || xlo) {
+            uint32_t hw[4], lw[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const u16 h0 = f2bf(v[2 * q]), h1 = f2bf(v[2 * q + 1]);
+                hw[q] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+                lw[q] = (uint32_t)f2bf(v[2 * q] - bf2f(h0)) | ((uint32_t)f2bf(v[2 * q + 1] - bf2f(h1)) << 16);
+            }
+            if (xhi) *(uint4 *)(xhi + e) = uint4{hw[0], hw[1], hw[2], hw[3]};
+            if (xlo) *(uint4 *)(xlo + e) = uint4{lw[0], lw[1], lw[2], lw[3]};
+        }
     }
 }
 
@@ -570,8 +605,9 @@ int launch_prep_xt(int esize, const void *X, int64_t rs, int64_t cs, int64_t p, 
 int launch_prep_x(int esize, const void *X, int64_t rs, int64_t cs, int64_t p, int64_t n, int64_t Ppad,
                   int64_t Kx, float *x32, uint16_t *xhi, uint16_t *xlo, hipStream_t s)
 {
-    const int64_t total = Ppad * Kx;
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 1 << 16));
+    if (Kx % 8 != 0) return -1;
+    const int64_t total8 = Ppad * Kx / 8;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((total8 + 255) / 256, 1 << 16));
     if (esize == 4)
         hipLaunchKernelGGL(prep_x_kernel<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s, (const uint32_t *)X,
                            rs, cs, p, n, Ppad, Kx, x32, xhi, xlo);
