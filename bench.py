@@ -309,7 +309,9 @@ def vectors_bench(args):
         roof = {"bound": "hbm", "achieved": round(nbytes / (ms * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4)
     roof["traffic"] = None
-    roof["kernel"] = "vec_partial_kernel + vec_reduce_kernel (%.3f GFLOP, %.1f MB algorithmic per call)" % (
+    kernels = ("vec_block3_kernel + vec_rows_kernel + vec_dot_kernel" if m == 3 and b in (4, 8, 16)
+               else "vec_partial_kernel + vec_reduce_kernel")
+    roof["kernel"] = kernels + " (%.3f GFLOP, %.1f MB algorithmic per call)" % (
         flops / 1e9, nbytes / 1e6)
     out = {"metric": "batched vector products A x^(m-1), A x^m GFLOP/s (each stored term once)",
            "value": round(flops / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
@@ -441,7 +443,7 @@ def source_digest():
     types."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("kernels.hip", "stage_bf16.hip", "plan.cpp", "common.hpp"):
+    for name in ("kernels.hip", "stage_bf16.hip", "stage_b64.hip", "plan.cpp", "common.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1301_7744_amd", "csrc", name), "rb").read())
     return h.hexdigest()
 
