@@ -377,13 +377,31 @@ int launch_levels(const Plan *P, const bcss_layout *A, const void *A_dev, const 
         xhi_read = (const uint16_t *)X_dev;
         xhi = nullptr;
     }
+    // Likewise the fp32 panel for an fp32 X of the panel's layout.
+    const float *x32_read = x32;
+    if (x32 && A->dtype == STTSM_F32 && cs_x == 1 && rs_x == P->Kx && P->n == P->Kx && P->p == P->Ppad &&
+        ((uintptr_t)X_dev & 15) == 0) {
+        x32_read = (const float *)X_dev;
+        x32 = nullptr;
+    }
     if ((x32 || xhi || xlo) &&
         launch_prep_x(dtype_size(A->dtype), X_dev, rs_x, cs_x, P->p, P->n, P->Ppad, P->Kx, x32, xhi, xlo, s))
         return fail(STTSM_EHIP, std::string("X panel launch failed: ") + hipGetErrorString(hipGetLastError()));
     float *xt = P->xp_off[3] >= 0 ? (float *)(w + P->xp_off[3]) : nullptr;
-    if (xt && launch_prep_xt(dtype_size(A->dtype), X_dev, rs_x, cs_x, P->p, P->n, P->Kt, P->Pt, xt, s))
+    // The FP32 block-copy kernel stages an fp32 X with contiguous, 16-byte
+    // aligned rows and n a multiple of 4 itself (transposed into LDS), in
+    // place of the transposed panel.
+    // STTSM_X_PANEL=1 keeps the panel, for measurement.
+    static const bool force_panel = [] {
+        const char *e = getenv("STTSM_X_PANEL");
+        return e && atoi(e) == 1;
+    }();
+    const bool x_direct = xt && !force_panel && A->dtype == STTSM_F32 && cs_x == 1 && rs_x % 4 == 0 &&
+                          P->n % 4 == 0 && ((uintptr_t)X_dev & 15) == 0;
+    if (xt && !x_direct &&
+        launch_prep_xt(dtype_size(A->dtype), X_dev, rs_x, cs_x, P->p, P->n, P->Kt, P->Pt, xt, s))
         return fail(STTSM_EHIP, std::string("X panel launch failed: ") + hipGetErrorString(hipGetLastError()));
-    const void *slot_ptr[4] = {x32, xhi_read, xlo, xt};
+    const void *slot_ptr[4] = {x32_read, xhi_read, xlo, x_direct ? X_dev : (const void *)xt};
     for (int d = 0; d <= last; ++d) {
         const StagePlan &S = P->stages[d];
         StageArgs a = S.args;
@@ -401,6 +419,10 @@ int launch_levels(const Plan *P, const bcss_layout *A, const void *A_dev, const 
         a.out = d == last ? out : (void *)(w + S.out_ws);
         a.xp = slot_ptr[S.xp_slot];
         a.xp_lo = S.xp_lo_slot >= 0 ? slot_ptr[S.xp_lo_slot] : nullptr;
+        a.x_direct = S.xp_slot == 3 && x_direct;
+        a.x_p = (int32_t)P->p;
+        a.x_n = (int32_t)P->n;
+        a.x_rs = rs_x;
         const long slot = prof_slot(S.d);
         if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot], s);
         const int lrc = S.b64         ? launch_stage_b64(a, S.tile.NT, s)

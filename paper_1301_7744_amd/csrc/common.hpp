@@ -136,6 +136,13 @@ struct StageArgs {
     int32_t accumulate;
     // X-resident bf16 kernel: one record per task, in task order.
     const XresRec *xrec;
+    // FP32 block-copy kernel: 1 when xp is the caller's fp32 X itself
+    // (rows of x_rs entries, x_p rows of x_n entries, x_n a multiple of 4,
+    // 16-byte aligned) instead of the transposed panel, staged transposed
+    // into LDS with zeros past p and n.
+    int32_t x_direct;
+    int32_t x_p, x_n;
+    int64_t x_rs;
 };
 
 

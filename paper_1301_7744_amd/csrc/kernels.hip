@@ -1315,6 +1315,9 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
     const float *in = (const float *)a.in;
     const float *xt = (const float *)a.xp;
     const int64_t xs = a.xt_stride;
+    const bool xdir = a.x_direct != 0;
+    const int64_t xrs = a.x_rs;
+    const int xp_rows = a.x_p, xp_cols = a.x_n;
 
     for (int i = tid; i < nbar; i += 256) {
         const InEntry ie = a.in_tab[g.in_row + i];
@@ -1421,9 +1424,19 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
 #pragma unroll
         for (int f = 0; f < XF; ++f) {
             const int v = tid + 256 * f;
-            const int xk = v / (NT / 4), xn = (v % (NT / 4)) * 4;
-            const int xc = xn < ncol ? xn : 0;   // columns past the tile are never used: stay in bounds
-            if (v < XV) rx[st][f] = *(const f32x4 *)(xt + (int64_t)(cx * KT + xk) * xs + n0 + xc);
+            if (xdir) {
+                // X itself: column n0 + xn of the tile is row n0 + xn of X,
+                // four consecutive k of it per float4 (zero past p and n)
+                const int xn = v / (KT / 4), xk = (v % (KT / 4)) * 4;
+                const int row = n0 + xn, kk = cx * KT + xk;
+                const bool ok = v < XV && row < xp_rows && kk < xp_cols;
+                rx[st][f] = *(const f32x4 *)(xt + (ok ? (int64_t)row * xrs + kk : 0));
+                if (!ok) rx[st][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+            } else {
+                const int xk = v / (NT / 4), xn = (v % (NT / 4)) * 4;
+                const int xc = xn < ncol ? xn : 0;   // columns past the tile are never used: stay in bounds
+                if (v < XV) rx[st][f] = *(const f32x4 *)(xt + (int64_t)(cx * KT + xk) * xs + n0 + xc);
+            }
         }
         read_tab(c + 1);
     };
@@ -1466,8 +1479,18 @@ __global__ __launch_bounds__(256, 2) void stage_fast_f32(const StageArgs a)
 #pragma unroll
         for (int f = 0; f < XF; ++f) {
             const int v = tid + 256 * f;
-            const int xk = v / (NT / 4), xn = (v % (NT / 4)) * 4;
-            if (v < XV) *(f32x4 *)&s_x[buf][xk * XS + xn] = rx[st][f];
+            if (xdir) {   // four k rows of one column
+                const int xn = v / (KT / 4), xk = (v % (KT / 4)) * 4;
+                if (v < XV) {
+                    s_x[buf][xk * XS + xn] = rx[st][f][0];
+                    s_x[buf][(xk + 1) * XS + xn] = rx[st][f][1];
+                    s_x[buf][(xk + 2) * XS + xn] = rx[st][f][2];
+                    s_x[buf][(xk + 3) * XS + xn] = rx[st][f][3];
+                }
+            } else {
+                const int xk = v / (NT / 4), xn = (v % (NT / 4)) * 4;
+                if (v < XV) *(f32x4 *)&s_x[buf][xk * XS + xn] = rx[st][f];
+            }
         }
     };
 
