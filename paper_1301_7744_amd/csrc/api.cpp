@@ -371,15 +371,18 @@ int launch_levels(const Plan *P, const bcss_layout *A, const void *A_dev, const 
     // A bf16 X that already has the bf16 panel's layout (rows of exactly Kx
     // = n entries, 16-byte aligned, no padding rows or columns) is read in
     // place: the panel would be a copy of it, entry for entry.
+    // STTSM_X_PANEL=1 builds every panel, for measurement and tests.
+    const char *xpe0 = getenv("STTSM_X_PANEL");
+    const bool keep_panels = xpe0 && atoi(xpe0) == 1;
     const uint16_t *xhi_read = xhi;
-    if (xhi && A->dtype == STTSM_BF16 && cs_x == 1 && rs_x == P->Kx && P->n == P->Kx && P->p == P->Ppad &&
+    if (xhi && !keep_panels && A->dtype == STTSM_BF16 && cs_x == 1 && rs_x == P->Kx && P->n == P->Kx && P->p == P->Ppad &&
         ((uintptr_t)X_dev & 15) == 0) {
         xhi_read = (const uint16_t *)X_dev;
         xhi = nullptr;
     }
     // Likewise the fp32 panel for an fp32 X of the panel's layout.
     const float *x32_read = x32;
-    if (x32 && A->dtype == STTSM_F32 && cs_x == 1 && rs_x == P->Kx && P->n == P->Kx && P->p == P->Ppad &&
+    if (x32 && !keep_panels && A->dtype == STTSM_F32 && cs_x == 1 && rs_x == P->Kx && P->n == P->Kx && P->p == P->Ppad &&
         ((uintptr_t)X_dev & 15) == 0) {
         x32_read = (const float *)X_dev;
         x32 = nullptr;
@@ -391,12 +394,7 @@ int launch_levels(const Plan *P, const bcss_layout *A, const void *A_dev, const 
     // The FP32 block-copy kernel stages an fp32 X with contiguous, 16-byte
     // aligned rows and n a multiple of 4 itself (transposed into LDS), in
     // place of the transposed panel.
-    // STTSM_X_PANEL=1 keeps the panel, for measurement.
-    static const bool force_panel = [] {
-        const char *e = getenv("STTSM_X_PANEL");
-        return e && atoi(e) == 1;
-    }();
-    const bool x_direct = xt && !force_panel && A->dtype == STTSM_F32 && cs_x == 1 && rs_x % 4 == 0 &&
+    const bool x_direct = xt && !keep_panels && A->dtype == STTSM_F32 && cs_x == 1 && rs_x % 4 == 0 &&
                           P->n % 4 == 0 && ((uintptr_t)X_dev & 15) == 0;
     if (xt && !x_direct &&
         launch_prep_xt(dtype_size(A->dtype), X_dev, rs_x, cs_x, P->p, P->n, P->Kt, P->Pt, xt, s))

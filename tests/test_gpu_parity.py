@@ -779,3 +779,27 @@ def test_bf16_b64_kernel(m, n, p):
     assert np.all(got[padding_mask(m, p, b)] == 0.0)
     if n == 4096:
         check_literal_entries({PBF: got}, A, X, b, ref, S, n)
+
+
+# ------------------------------------------------------------------ X read in place
+X_PLACE_CASES = [(3, 256, 256, 16, P32), (3, 100, 70, 16, P32), (3, 130, 60, 16, P32), (3, 64, 64, 16, PBF),
+                 (2, 256, 256, 64, P32), (2, 256, 256, 64, PBF), (4, 40, 37, 8, P32)]
+
+
+@pytest.mark.parametrize("m,n,p,b,prec", X_PLACE_CASES)
+def test_x_in_place_equals_panels(m, n, p, b, prec, monkeypatch):
+    """X read in place (an X of the panel's layout, or the FP32 block-copy
+    kernel staging X itself, zeros past p and n) gives C bit for bit equal to
+    the padded panels (STTSM_X_PANEL=1), for shapes that take either path."""
+    import torch
+    A = synth.symmetric_uniform(m, n, (m, n, p, 171))
+    X = synth.change_of_basis(p, n, (m, n, p, 172))
+    tdt = torch.bfloat16 if prec == PBF else torch.float32
+    if prec == PBF:
+        A, X = synth.round_to_bf16(A), synth.round_to_bf16(X)
+    monkeypatch.delenv("STTSM_X_PANEL", raising=False)
+    got = run(A, X, b, b, prec, dtype=tdt)
+    monkeypatch.setenv("STTSM_X_PANEL", "1")
+    ref = run(A, X, b, b, prec, dtype=tdt)
+    say("x in place", (m, n, p, b, prec))
+    assert np.array_equal(got, ref)
