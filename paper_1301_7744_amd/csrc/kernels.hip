@@ -1138,10 +1138,11 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
             }
 }
 
-// bf16: at most 128 VGPRs, so that four workgroups fit per CU as for FP32
-// (the tile is latency-bound: m6_n24_b4 bf16 ran at three per CU with 138).
+// bf16 tiles of up to 128 rows: at most 128 VGPRs, so that four workgroups
+// fit per CU as for FP32 (the tile is latency-bound: m6_n24_b4 bf16 ran at
+// three per CU with 138); 256-row tiles are held to two by their LDS.
 template <int CMP, int MT, int NT, int WM, int WN, bool B_IS_IN, bool FIRST>
-__global__ __launch_bounds__(256, CMP == CMP_BF16 ? 4 : 1) void stage_kernel(const StageArgs a)
+__global__ __launch_bounds__(256, CMP == CMP_BF16 && MT <= 128 ? 4 : 1) void stage_kernel(const StageArgs a)
 {
     __shared__ GenericSmem<CMP, MT, NT> sm;
     generic_tile<CMP, MT, NT, WM, WN, B_IS_IN>(a, a.tasks[blockIdx.x], sm);

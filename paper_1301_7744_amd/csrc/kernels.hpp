@@ -31,6 +31,11 @@ bool bf16_fast_supported(int m, int bA, int bC, int nbar);
 void bf16_fast_tile(int b, int *MT, int *NT, int *KT, int *PD);   // the default tile
 bool bf16_tile_supported(int b, int NT, int KT, int PD);
 int launch_stage_bf16(const StageArgs &a, int NT, int KT, int PD, bool xres, hipStream_t s);
+// Grouped persistent X-resident form (the server): tasks as for the other
+// grouped kernels; all stages share (m, k, NT, PD); the stages' xrec is not
+// read (each record is assembled from the row group and input tables).
+int launch_grouped_xres(int m, int k, int NT, int PD, const StageArgs *d_stages, const GroupedTask *d_tasks,
+                        int ntasks, int *d_head, int grid, hipStream_t s);
 // bf16 kernel for m = 2 with 64 x 64 blocks (stage_b64.hip): 256-row tiles of
 // four row groups, NT in {128, 192, 256} columns, eight waves.
 bool b64_bf16_supported(int m, int bA, int bC, int nbar, bool bf16_input);

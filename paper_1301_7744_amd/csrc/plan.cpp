@@ -64,6 +64,7 @@ bool PlanKey::operator<(const PlanKey &o) const
     if (in_dtype != o.in_dtype) return in_dtype < o.in_dtype;
     if (grouped != o.grouped) return grouped < o.grouped;
     if (generic_only != o.generic_only) return generic_only < o.generic_only;
+    if (xres_records != o.xres_records) return xres_records < o.xres_records;
     return overrides < o.overrides;
 }
 
@@ -738,7 +739,7 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err, int cus)
             order_tasks_by_task_key(&S.tasks, [](const Task &t) {
                 return (int64_t)(t.group / 16) * 65536 + t.nt / 8;
             });
-        } else if (S.tile.xres) {
+        } else if (S.tile.xres && key.xres_records) {
             // Locality key of a row group: below the first level the groups
             // of one C-block tuple J' read only that tuple's slab of the
             // input temporary; at the first level a stored A block is read
@@ -756,7 +757,7 @@ bool plan_build_host(const PlanKey &key, Plan *P, std::string *err, int cus)
             *err = "too many tasks";
             return false;
         }
-        if (S.tile.xres) {
+        if (S.tile.xres && key.xres_records) {
             // One record per task, in the final task order.
             if (nbar > 16) {
                 *err = "X-resident kernel: more than 16 input blocks";

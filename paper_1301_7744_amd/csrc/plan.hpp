@@ -95,6 +95,9 @@ struct PlanKey {
     int bA, bC, prec, in_dtype;
     bool generic_only = false;   // force the generic staging kernel (testing)
     bool grouped = false;        // tiles of the grouped kernel (serving)
+    // X-resident levels: per-task records and the XCD locality order of the
+    // tasks (the server's grouped X-resident kernel reads neither).
+    bool xres_records = true;
     // The measurement overrides of the tile choice in force when the plan was
     // built (STTSM_FAST_TILE, STTSM_BF16_TILE, STTSM_NARROW_MT,
     // STTSM_WIDE_MT), so that a plan is never reused under other overrides.

@@ -35,11 +35,14 @@ using namespace symt;
 namespace {
 
 // Kernel class of a stage in a server round: the compute form (generic
-// grouped kernel), or one (m, b, k) of the block-copy bf16 kernel.
-constexpr int kLaunchClasses = CMP_X3 + 1 + 2 * 2 * 4;
+// grouped kernel), one (m, b, k) of the block-copy bf16 kernel, or one
+// (m, k) of the X-resident bf16 kernel (b = 16).
+constexpr int kXresClass0 = CMP_X3 + 1 + 2 * 2 * 4;
+constexpr int kLaunchClasses = kXresClass0 + 2 * 4;
 int launch_class(int m, int b, const StagePlan &St)
 {
     if (!St.fast_bf16) return St.compute;
+    if (St.tile.xres) return kXresClass0 + (m - 3) * 4 + St.k;
     return CMP_X3 + 1 + ((m - 3) * 2 + (b == 16 ? 1 : 0)) * 4 + St.k;
 }
 
@@ -98,6 +101,31 @@ struct Footprint {
     size_t off_a = 0, off_x = 0, off_ws = 0, off_tab = 0;
     std::vector<size_t> off_groups, off_in;   // per level, inside the table area
 };
+
+// The plan a request runs.  bf16 requests take the plain path's tiles when
+// every level is X-resident or has the bf16 block-copy kernel's default tile
+// (the X-resident levels then run in the grouped X-resident kernel, the
+// others in the grouped block-copy kernel, both with the plain path's
+// arithmetic, so results are bit-identical to it); otherwise the plan is
+// built with the grouped kernels' tiles throughout.
+bool server_plan(PlanKey key, Plan *P, std::string *why)
+{
+    key.generic_only = false;
+    key.grouped = false;
+    key.xres_records = false;
+    if (plan_build_host(key, P, why)) {
+        bool ok = true;
+        for (const StagePlan &St : P->stages) {
+            int mt, nt, kt, pd;
+            bf16_fast_tile(St.args.bA, &mt, &nt, &kt, &pd);
+            ok = ok && St.fast_bf16 && (St.tile.xres || (St.tile.NT == nt && St.tile.KT == kt && St.tile.PD == pd));
+        }
+        if (ok) return true;
+    }
+    *P = Plan();
+    key.grouped = true;
+    return plan_build_host(key, P, why);
+}
 
 struct Req {
     uint64_t ticket = 0;
@@ -281,6 +309,7 @@ StageArgs stage_args_for(const Req *q, int d)
     a.xp_lo = St.xp_lo_slot >= 0 ? slot[St.xp_lo_slot] : nullptr;
     a.groups = (const GroupDesc *)(q->main + fp.off_tab + fp.off_groups[d]);
     a.in_tab = (const InEntry *)(q->main + fp.off_tab + fp.off_in[d]);
+    a.xrec = nullptr;   // the grouped X-resident kernel assembles its records from the tables
     a.tasks = nullptr;
     return a;
 }
@@ -428,6 +457,7 @@ void worker_loop(sttsm_server *S)
             size_t ti = 0;
             size_t cls_t0[kLaunchClasses] = {}, cls_cnt[kLaunchClasses] = {};
             int cls_m[kLaunchClasses] = {}, cls_b[kLaunchClasses] = {}, cls_k[kLaunchClasses] = {};
+            int cls_nt[kLaunchClasses] = {}, cls_pd[kLaunchClasses] = {};
             for (int cls = 0; cls < kLaunchClasses; ++cls) {
                 cls_t0[cls] = ti;
                 for (size_t i = 0; i < active.size(); ++i) {
@@ -439,6 +469,8 @@ void worker_loop(sttsm_server *S)
                     cls_m[cls] = q->plan->m;
                     cls_b[cls] = q->plan->bA;
                     cls_k[cls] = St.k;
+                    cls_nt[cls] = St.tile.NT;
+                    cls_pd[cls] = St.tile.PD;
                 }
                 cls_cnt[cls] = ti - cls_t0[cls];
             }
@@ -458,6 +490,9 @@ void worker_loop(sttsm_server *S)
                 int *head = sl.d_heads + cls;
                 const int rc = cls < CMP_X3 + 1
                                    ? launch_grouped(cls, sl.d_stages, tk, cnt, head, S->grid, S->stream)
+                               : cls >= kXresClass0
+                                   ? launch_grouped_xres(cls_m[cls], cls_k[cls], cls_nt[cls], cls_pd[cls], sl.d_stages,
+                                                         tk, cnt, head, S->grid, S->stream)
                                    : launch_grouped_bf16(cls_m[cls], cls_b[cls], cls_k[cls], sl.d_stages, tk, cnt,
                                                          head, S->grid, S->stream);
                 if (rc) {
@@ -508,11 +543,9 @@ size_t sttsm_request_footprint(const sttsm_request *req)
     if (!req) return 0;
     PlanKey key;
     if (make_key(&req->A, &req->C, req->prec, &key) != STTSM_OK) return 0;
-    key.grouped = true;
-    key.generic_only = false;
     Plan P;
     std::string why;
-    if (!plan_build_host(key, &P, &why)) return 0;
+    if (!server_plan(key, &P, &why)) return 0;
     Footprint fp;
     if (compute_footprint(req, P, &fp) != STTSM_OK) return 0;
     return fp.main + fp.c;
@@ -565,13 +598,11 @@ int sttsm_submit(sttsm_server *S, const sttsm_request *req, uint64_t *ticket)
     PlanKey key;
     int rc = make_key(&req->A, &req->C, req->prec, &key);
     if (rc != STTSM_OK) return rc;
-    key.grouped = true;
-    key.generic_only = false;
     std::unique_ptr<Req> q(new Req);
     q->r = *req;
     q->plan.reset(new Plan);
     std::string why;
-    if (!plan_build_host(key, q->plan.get(), &why)) return fail(STTSM_EINVAL, why);
+    if (!server_plan(key, q->plan.get(), &why)) return fail(STTSM_EINVAL, why);
     if ((rc = compute_footprint(req, *q->plan, &q->fp)) != STTSM_OK) return fail(rc, "bad request layout");
     if (q->fp.main + q->fp.c > S->arena_bytes)
         return fail(STTSM_ENOMEM, "request footprint exceeds the whole arena");

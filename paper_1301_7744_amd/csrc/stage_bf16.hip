@@ -496,8 +496,16 @@ struct XresSmem {
 constexpr int kXresRecWords = (int)(sizeof(XresRec) / 8);
 static_assert(sizeof(XresRec) % 8 == 0 && kXresRecWords <= 64, "a record is a few 8-byte words");
 
-template <int M, int K, int PD, int XNT>
-__global__ __launch_bounds__(256, XNT == 128 ? 1 : 2) void stage_xres_bf16(const StageArgs a)
+// The X-resident tile loop.  GROUPED = false: the tasks of one stage `a1`,
+// task t on workgroup t mod gridDim.x, each record loaded one task ahead.
+// GROUPED = true (the server): tasks of many stages of one (M, K), each
+// naming its stage, row group and tile (GroupedTask), task t on workgroup
+// t mod gridDim.x; the stage's values are read per task and its record is
+// assembled from the stage's tables (no record table is uploaded).
+template <int M, int K, int PD, int XNT, bool GROUPED>
+__device__ __forceinline__ void xres_run(const StageArgs &a1, const StageArgs *__restrict__ stages,
+                                         const GroupedTask *__restrict__ gtasks, int ngtasks,
+                                         int *__restrict__ queue_head, XresSmem<M, K, XNT> &sm, int *s_task)
 {
     constexpr int B = 16, NT = XNT, KT = 16;
     using C = Bf16Cfg<M, B, K, 64, KT>;
@@ -508,20 +516,18 @@ __global__ __launch_bounds__(256, XNT == 128 ? 1 : 2) void stage_xres_bf16(const
     constexpr int XVT = NT * kXresMaxK / 8 / 256;   // X-slice vectors per thread (at most)
     static_assert(C::G == 1 && C::VEC == 512 && NV == 2 && PART == 512, "one whole block part per chunk");
     static_assert(C::DUAL || C::KM, "per-block regions or [row][kk]");
-    __shared__ XresSmem<M, K, XNT> sm;
-
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int r32 = lane & 31, half = lane >> 5;
     const int grp = lane >> 4, gl = lane & 15;
-    const u16 *in = (const u16 *)a.in;
-    const u16 *xp = (const u16 *)a.xp;
-    const int64_t *recw = (const int64_t *)a.xrec;
-    const int nbar = a.nbar;
-    const int nch_pad = (nbar + PD - 1) / PD * PD;
-    const int64_t Kx = a.Kx, Ppad = a.Ppad;
-    const int kvec = a.Kpad / 8;            // 16-byte vectors per X row
-    const int xv_count = NT * kvec;
+    // Values of the stage (per launch, or per task when grouped).
+    const u16 *in = (const u16 *)a1.in;
+    const u16 *xp = (const u16 *)a1.xp;
+    int nbar = a1.nbar;
+    int nch_pad = (nbar + PD - 1) / PD * PD;
+    int64_t Kx = a1.Kx, Ppad = a1.Ppad;
+    int kvec = a1.Kpad / 8;                 // 16-byte vectors per X row
+    int xv_count = NT * kvec;
 
     // Digits of this thread's two vectors in the block part (fixed).
     int vd0[NV], vd1[NV], vd2[NV];
@@ -533,14 +539,17 @@ __global__ __launch_bounds__(256, XNT == 128 ? 1 : 2) void stage_xres_bf16(const
         vd1[f] = w1 % B;
         vd2[f] = w1 / B;
     }
-    // X-slice vector v = tid + 256 f: its row and k offset (fixed).
+    // X-slice vector v = tid + 256 f: its row and k offset (fixed per stage).
     int xrow[XVT], xk[XVT];
+    auto x_slots = [&]() {
 #pragma unroll
-    for (int f = 0; f < XVT; ++f) {
-        const int v = tid + 256 * f;
-        xrow[f] = v / kvec;
-        xk[f] = (v - xrow[f] * kvec) * 8;
-    }
+        for (int f = 0; f < XVT; ++f) {
+            const int v = tid + 256 * f;
+            xrow[f] = v / kvec;
+            xk[f] = (v - xrow[f] * kvec) * 8;
+        }
+    };
+    if constexpr (!GROUPED) x_slots();
     // Per vector, its global and LDS offsets for insertion position q
     // (16 bits each: goff < b^m <= 65536, loff < 2^13), packed in 64-bit
     // words at bit 16 q: plain registers, selected with a uniform shift
@@ -554,13 +563,78 @@ __global__ __launch_bounds__(256, XNT == 128 ? 1 : 2) void stage_xres_bf16(const
     // tid % words (so the load is not behind a branch), the first `words`
     // threads store theirs.
     const int rw = tid % kXresRecWords;
-    int64_t next_word = blockIdx.x < (unsigned)a.ntasks ? recw[(int64_t)blockIdx.x * kXresRecWords + rw] : 0;
+    const int64_t *recw = (const int64_t *)a1.xrec;
+    int64_t next_word = 0;
+    // Grouped: task t on workgroup t mod gridDim.x as well; the next task's
+    // record is assembled from its stage's tables (row group, input table),
+    // loaded one task ahead: the row group's fields by every thread, input
+    // block tid's offset and insertion position by thread tid < nbar.
+    int nx_stage = 0, nx_q = 0, nx_jc = 0, nx_n0 = 0, nx_mt = 0;
+    int64_t nx_off = 0, nx_ob = 0, nx_ojs = 0;
+    auto grouped_prefetch = [&](int tn) {
+        const GroupedTask gt = gtasks[tn];
+        nx_stage = __builtin_amdgcn_readfirstlane(gt.stage);
+        const StageArgs &sa = stages[nx_stage];
+        const GroupDesc g = sa.groups[gt.group];
+        nx_ob = g.out_base;
+        nx_ojs = g.out_jstride;
+        nx_jc = g.jcount;
+        nx_n0 = gt.nt * NT;
+        nx_mt = gt.mt;
+        if (tid < sa.nbar) {
+            const InEntry e = sa.in_tab[g.in_row + tid];
+            nx_off = e.off;
+            nx_q = e.q;
+        }
+    };
+    if constexpr (!GROUPED)
+        next_word = blockIdx.x < (unsigned)a1.ntasks ? recw[(int64_t)blockIdx.x * kXresRecWords + rw] : 0;
+    else if (blockIdx.x < (unsigned)ngtasks)
+        grouped_prefetch(blockIdx.x);
 
-    for (int t = blockIdx.x; t < a.ntasks; t += gridDim.x) {
-        if (tid < kXresRecWords) sm.s_rec[tid] = next_word;
-        __syncthreads();
-        const int tn = t + gridDim.x;
-        next_word = recw[(int64_t)(tn < a.ntasks ? tn : t) * kXresRecWords + rw];
+    for (int t = blockIdx.x;; t += gridDim.x) {
+        int stage = 0;
+        if constexpr (GROUPED) {
+            if (t >= ngtasks) break;
+            stage = nx_stage;
+            XresRec *r = (XresRec *)sm.s_rec;
+            if (tid < 16) r->off[tid] = nx_off;
+            if (tid < 64) {   // wave 0: the insertion positions, two bits each
+                const uint64_t b0 = __builtin_amdgcn_ballot_w64(tid < 16 && (nx_q & 1));
+                const uint64_t b1 = __builtin_amdgcn_ballot_w64(tid < 16 && (nx_q & 2));
+                if (tid == 0) {
+                    uint32_t qb = 0;
+                    for (int i = 0; i < 16; ++i)
+                        qb |= (uint32_t)(((b0 >> i) & 1u) | (((b1 >> i) & 1u) << 1)) << (2 * i);
+                    r->q_bits = (int32_t)qb;
+                    r->out_base = nx_ob;
+                    r->out_jstride = nx_ojs;
+                    r->n0 = nx_n0;
+                    r->mt = nx_mt;
+                    r->jcount = nx_jc;
+                }
+            }
+            const StageArgs &sa = stages[stage];
+            in = (const u16 *)sa.in;
+            xp = (const u16 *)sa.xp;
+            nbar = sa.nbar;
+            nch_pad = (nbar + PD - 1) / PD * PD;
+            Kx = sa.Kx;
+            Ppad = sa.Ppad;
+            kvec = sa.Kpad / 8;
+            xv_count = NT * kvec;
+            x_slots();
+            __syncthreads();
+            const int tn = t + gridDim.x;
+            grouped_prefetch(tn < ngtasks ? tn : t);
+        } else {
+            if (t >= a1.ntasks) break;
+            if (tid < kXresRecWords) sm.s_rec[tid] = next_word;
+            __syncthreads();
+            const int tn = t + gridDim.x;
+            next_word = recw[(int64_t)(tn < a1.ntasks ? tn : t) * kXresRecWords + rw];
+        }
+        const StageArgs &a = GROUPED ? stages[stage] : a1;
         const XresRec *rec = (const XresRec *)sm.s_rec;
         const int n0 = __builtin_amdgcn_readfirstlane(rec->n0);
         const int mt = __builtin_amdgcn_readfirstlane(rec->mt);
@@ -757,6 +831,25 @@ __global__ __launch_bounds__(256, XNT == 128 ? 1 : 2) void stage_xres_bf16(const
     }
 }
 
+template <int M, int K, int PD, int XNT>
+__global__ __launch_bounds__(256, XNT == 128 ? 1 : 2) void stage_xres_bf16(const StageArgs a)
+{
+    __shared__ XresSmem<M, K, XNT> sm;
+    xres_run<M, K, PD, XNT, false>(a, nullptr, nullptr, 0, nullptr, sm, nullptr);
+}
+
+// Grouped persistent form for the server: every task names its stage, row
+// group and tile; all stages of one launch share (M, K) and the tile.
+template <int M, int K, int PD, int XNT>
+__global__ __launch_bounds__(256, XNT == 128 ? 1 : 2) void grouped_xres_bf16(const StageArgs *__restrict__ stages,
+                                                                             const GroupedTask *__restrict__ tasks,
+                                                                             int ntasks, int *__restrict__ queue_head)
+{
+    __shared__ XresSmem<M, K, XNT> sm;
+    xres_run<M, K, PD, XNT, true>(stages[0], stages, tasks, ntasks, queue_head, sm, nullptr);
+}
+
+
 // Default tile (NT, KT, PD) per block size; the grouped kernel always uses it.
 template <int B>
 struct Bf16Default {
@@ -891,6 +984,22 @@ int launch_xres_k(const StageArgs &a, int NT, int PD, hipStream_t s)
     return 0;
 }
 
+template <int M, int K>
+int launch_grouped_xres_k(int NT, int PD, const StageArgs *d_stages, const GroupedTask *d_tasks, int ntasks,
+                          int *d_head, int grid, hipStream_t s)
+{
+    const int per_cu = NT == 128 ? 1 : 2;
+    const dim3 g((unsigned)std::max(1, std::min(std::min(grid, per_cu * current_cus()), ntasks))), b(256);
+#define STTSM_GX(nt, pd) \
+    if (NT == nt && PD == pd) { \
+        hipLaunchKernelGGL((grouped_xres_bf16<M, K, pd, nt>), g, b, 0, s, d_stages, d_tasks, ntasks, d_head); \
+        return 0; \
+    }
+    STTSM_GX(64, 2) STTSM_GX(64, 4) STTSM_GX(96, 2) STTSM_GX(96, 4) STTSM_GX(128, 2) STTSM_GX(128, 4)
+#undef STTSM_GX
+    return -1;
+}
+
 int launch_xres(const StageArgs &a, int NT, int PD, hipStream_t s)
 {
     if (a.m == 3) {
@@ -927,6 +1036,25 @@ int launch_stage_bf16(const StageArgs &a, int NT, int KT, int PD, bool xres, hip
         return hipGetLastError() == hipSuccess ? 0 : -1;
     }
     return launch_bf16_any(a.m, a.bA, a.k, a, NT, KT, PD, nullptr, nullptr, 0, nullptr, 0, s);
+}
+
+int launch_grouped_xres(int m, int k, int NT, int PD, const StageArgs *d_stages, const GroupedTask *d_tasks,
+                        int ntasks, int *d_head, int grid, hipStream_t s)
+{
+    if (ntasks <= 0) return 0;
+    int rc = -1;
+    if (m == 3) {
+        if (k == 0) rc = launch_grouped_xres_k<3, 0>(NT, PD, d_stages, d_tasks, ntasks, d_head, grid, s);
+        else if (k == 1) rc = launch_grouped_xres_k<3, 1>(NT, PD, d_stages, d_tasks, ntasks, d_head, grid, s);
+        else if (k == 2) rc = launch_grouped_xres_k<3, 2>(NT, PD, d_stages, d_tasks, ntasks, d_head, grid, s);
+    } else if (m == 4) {
+        if (k == 0) rc = launch_grouped_xres_k<4, 0>(NT, PD, d_stages, d_tasks, ntasks, d_head, grid, s);
+        else if (k == 1) rc = launch_grouped_xres_k<4, 1>(NT, PD, d_stages, d_tasks, ntasks, d_head, grid, s);
+        else if (k == 2) rc = launch_grouped_xres_k<4, 2>(NT, PD, d_stages, d_tasks, ntasks, d_head, grid, s);
+        else if (k == 3) rc = launch_grouped_xres_k<4, 3>(NT, PD, d_stages, d_tasks, ntasks, d_head, grid, s);
+    }
+    if (rc) return rc;
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_grouped_bf16(int m, int b, int k, const StageArgs *d_stages, const GroupedTask *d_tasks, int ntasks,
