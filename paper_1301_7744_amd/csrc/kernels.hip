@@ -751,7 +751,11 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
     const bool in_f32 = CMP == CMP_BF16 ? a.in_f32 != 0 : true;
     const float *in32 = (const float *)a.in;
     const u16 *in16 = (const u16 *)a.in;
-    const InEntry *row = a.in_tab + g.in_row;
+    // The row group's input table in global memory (typed so: a read that
+    // may come from LDS or from here would otherwise become one flat load,
+    // which counts on both wait counters).
+    typedef __attribute__((address_space(1))) const InEntry gInEntry;
+    gInEntry *row = (gInEntry *)a.in_tab + g.in_row;
 
     __syncthreads();
 
@@ -777,9 +781,8 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
                 ioff = sm.s_ioff[blk0];
                 iq = sm.s_iq[blk0];
             } else {
-                const InEntry ie = row[blk0];
-                ioff = ie.off;
-                iq = ie.q;
+                ioff = row[blk0].off;
+                iq = row[blk0].q;
             }
             const int sk = sm.s_sqk[iq];
             const bool kfast = sk == 1;
@@ -840,9 +843,8 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
                         ioff = sm.s_ioff[blk0 + gi];
                         iq = sm.s_iq[blk0 + gi];
                     } else {
-                        const InEntry ie = row[blk0 + gi];
-                        ioff = ie.off;
-                        iq = ie.q;
+                        ioff = row[blk0 + gi].off;
+                        iq = row[blk0 + gi].q;
                     }
                     const int sk = sm.s_sqk[iq];
                     const int64_t off = ioff + s_mpart[iq][mm] + (int64_t)lk * sk;
@@ -894,9 +896,8 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
                                 ioff = sm.s_ioff[blk0 + gi];
                                 iq = sm.s_iq[blk0 + gi];
                             } else {
-                                const InEntry ie = row[blk0 + gi];
-                                ioff = ie.off;
-                                iq = ie.q;
+                                ioff = row[blk0 + gi].off;
+                                iq = row[blk0 + gi].q;
                             }
                             const int sk = sm.s_sqk[iq];
                             const int64_t off = ioff + s_mpart[iq][mm] + (int64_t)lk * sk;
@@ -941,9 +942,8 @@ __device__ __forceinline__ void generic_tile(const StageArgs &a, const Task task
                                 ioff = sm.s_ioff[blk0 + gi];
                                 iq = sm.s_iq[blk0 + gi];
                             } else {
-                                const InEntry ie = row[blk0 + gi];
-                                ioff = ie.off;
-                                iq = ie.q;
+                                ioff = row[blk0 + gi].off;
+                                iq = row[blk0 + gi].q;
                             }
                             const int64_t off = ioff + s_mpart[iq][mm] + (int64_t)lk * sm.s_sqk[iq];
                             in_f[t][e] = in_f32 ? in32[off] : bf2f(in16[off]);

@@ -143,6 +143,17 @@ __device__ __forceinline__ void place(int d0, int d1, int d2, const int *fixed_d
     *along_k = !KM && pk == 0;
 }
 
+// Global-memory view of a 16-byte vector: the grouped form reads its input
+// and X pointers from the stage table, where the compiler cannot see their
+// address space; flat loads would count on both wait counters and every
+// prefetched chunk would be waited for at once.
+typedef __attribute__((address_space(1))) const u32x4 gu32x4;
+typedef __attribute__((address_space(1))) const GroupDesc gGroupDesc;
+typedef __attribute__((address_space(1))) const InEntry gInEntry;
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) u16 gu16;
+typedef __attribute__((address_space(1))) u32x4 gu32x4w;
+
 template <int M, int B, int K, int NT, int KT, int PD>
 __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, Bf16Smem<M, B, K, NT, KT> &sm)
 {
@@ -155,7 +166,7 @@ __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, B
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
-    const GroupDesc gd = a.groups[task.group];
+    gGroupDesc &gd = ((gGroupDesc *)a.groups)[task.group];
     const int n0 = task.nt * NT;
     const int Nvalid = gd.jcount * B;
     const int nbar = a.nbar;
@@ -175,9 +186,9 @@ __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, B
         }
     }
     for (int i = tid; i < nbar; i += 256) {
-        const InEntry ie = a.in_tab[gd.in_row + i];
-        sm.s_ioff[i] = ie.off;
-        sm.s_iq[i] = ie.q;
+        gInEntry *ie = (gInEntry *)a.in_tab + gd.in_row + i;
+        sm.s_ioff[i] = ie->off;
+        sm.s_iq[i] = ie->q;
     }
     // This thread's vectors: block g of the chunk and digits in the part.
     // Threads beyond the chunk's vector count (only when it is not a
@@ -235,7 +246,7 @@ __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, B
             rv[u][f] = valid;
             if constexpr (C::DUAL)
                 if ((256 * f) % PART == 0) rkm[u][(256 * f) / PART] = q == 0;
-            rin[u][f] = *(const u32x4 *)(in + sm.s_ioff[ibc] + goff);
+            rin[u][f] = *(const gu32x4 *)(in + sm.s_ioff[ibc] + goff);
         }
 #pragma unroll
         for (int f = 0; f < NXV; ++f) {
@@ -245,7 +256,7 @@ __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, B
             const int64_t ng = n0 + row, kg = (int64_t)c * KT + kv;
             const bool ok = ng < Ppad && kg < Kpad;
             rxv[u][f] = ok;
-            rx[u][f] = *(const u32x4 *)(xp + (ok ? ng * Kx + kg : 0));
+            rx[u][f] = *(const gu32x4 *)(xp + (ok ? ng * Kx + kg : 0));
         }
     };
     auto store_chunk = [&](int buf, int u) {
@@ -379,12 +390,12 @@ __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, B
         // C in fp32.  Lanes run along the output columns, whose C-block mode
         // is mode 0 (stride 1): each store covers 2 x 128 contiguous bytes.
         if (wave_live) {
-            float *out = (float *)a.out;
+            gfloat *out = (gfloat *)a.out;
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
                 const int ng = n0 + wn * WTN + j * 32 + r32;
                 if (ng < Nvalid) {
-                    float *oj = out + npart(ng);
+                    gfloat *oj = out + npart(ng);
 #pragma unroll
                     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -401,7 +412,7 @@ __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, B
         // [column][row] and writes it back as 16-byte row runs.
         __syncthreads();   // every wave is done with the staging buffers
         u16 *so = sm.s_out[wave];
-        u16 *out = (u16 *)a.out;
+        gu16 *out = (gu16 *)a.out;
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -421,7 +432,7 @@ __device__ __forceinline__ void bf16_tile(const StageArgs &a, const Task task, B
                     const u32x4 w = *(const u32x4 *)&so[col * kOutRow + run];
                     const int ng = n0 + wn * WTN + j * 32 + col;
                     const int mm = wm * WTM + i * 32 + run;
-                    if (wave_live && ng < Nvalid) *(u32x4 *)(out + npart(ng) + opart(mm)) = w;
+                    if (wave_live && ng < Nvalid) *(gu32x4w *)(out + npart(ng) + opart(mm)) = w;
                 }
                 __builtin_amdgcn_wave_barrier();
             }
@@ -575,16 +586,18 @@ __device__ __forceinline__ void xres_run(const StageArgs &a1, const StageArgs *_
         const GroupedTask gt = gtasks[tn];
         nx_stage = __builtin_amdgcn_readfirstlane(gt.stage);
         const StageArgs &sa = stages[nx_stage];
-        const GroupDesc g = sa.groups[gt.group];
-        nx_ob = g.out_base;
-        nx_ojs = g.out_jstride;
-        nx_jc = g.jcount;
+        // (fields read through global-space pointers: the table pointers
+        // come from memory, and flat loads would count on the LDS counter)
+        gGroupDesc *g = (gGroupDesc *)sa.groups + gt.group;
+        nx_ob = g->out_base;
+        nx_ojs = g->out_jstride;
+        nx_jc = g->jcount;
         nx_n0 = gt.nt * NT;
         nx_mt = gt.mt;
         if (tid < sa.nbar) {
-            const InEntry e = sa.in_tab[g.in_row + tid];
-            nx_off = e.off;
-            nx_q = e.q;
+            gInEntry *e = (gInEntry *)sa.in_tab + g->in_row + tid;
+            nx_off = e->off;
+            nx_q = e->q;
         }
     };
     if constexpr (!GROUPED)
@@ -648,7 +661,7 @@ __device__ __forceinline__ void xres_run(const StageArgs &a1, const StageArgs *_
         for (int f = 0; f < XVT; ++f) {
             const int64_t ng = n0 + xrow[f];
             const bool ok = tid + 256 * f < xv_count && ng < Ppad;
-            xr[f] = *(const u32x4 *)(xp + (ok ? ng * Kx + xk[f] : 0));
+            xr[f] = *(const gu32x4 *)(xp + (ok ? ng * Kx + xk[f] : 0));
             if (!ok) xr[f] = u32x4{0u, 0u, 0u, 0u};
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -680,6 +693,12 @@ __device__ __forceinline__ void xres_run(const StageArgs &a1, const StageArgs *_
             cur_mt = mt;
         }
 
+        // The task's input-block offsets, one per lane (lane i holds block
+        // i's): a chunk's offset is a readlane, with no LDS access on the
+        // path from one chunk's barrier to the next chunk's loads.
+        const int64_t lane_off = rec->off[lane & 15];
+        const uint32_t off_lo = (uint32_t)lane_off, off_hi = (uint32_t)((uint64_t)lane_off >> 32);
+
         u32x4 rin[PD][NV];
         int rl[PD][NV];
         bool rv[PD], rq0[PD];
@@ -687,9 +706,8 @@ __device__ __forceinline__ void xres_run(const StageArgs &a1, const StageArgs *_
             const bool valid = c < nbar;
             const int ib = valid ? c : 0;
             const int q = (int)((q_bits >> (2 * ib)) & 3u);
-            const int64_t off = rec->off[ib];
-            const uint32_t olo = __builtin_amdgcn_readfirstlane((uint32_t)off);
-            const uint32_t ohi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)off >> 32));
+            const uint32_t olo = __builtin_amdgcn_readlane(off_lo, ib);
+            const uint32_t ohi = __builtin_amdgcn_readlane(off_hi, ib);
             const u16 *blk = in + (int64_t)(((uint64_t)ohi << 32) | olo);
             rv[u] = valid;
             rq0[u] = q == 0;
@@ -697,8 +715,8 @@ __device__ __forceinline__ void xres_run(const StageArgs &a1, const StageArgs *_
             const int go0 = (int)((gpk0 >> sh) & 0xFFFFu), go1 = (int)((gpk1 >> sh) & 0xFFFFu);
             rl[u][0] = (int)((lpk0 >> sh) & 0xFFFFu);
             rl[u][1] = (int)((lpk1 >> sh) & 0xFFFFu);
-            rin[u][0] = *(const u32x4 *)(blk + go0);
-            rin[u][1] = *(const u32x4 *)(blk + go1);
+            rin[u][0] = *(const gu32x4 *)(blk + go0);
+            rin[u][1] = *(const gu32x4 *)(blk + go1);
         };
         auto store_chunk = [&](int buf, int u) {
             u16 *si = sm.s_in[buf];
@@ -725,9 +743,10 @@ __device__ __forceinline__ void xres_run(const StageArgs &a1, const StageArgs *_
 #pragma unroll
                 for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-        auto mfma_chunk = [&](int buf, int c, bool km) {
+        // Operands of chunk c (block part from buffer buf, X slice columns
+        // c KT .. c KT + KT - 1), then its MFMAs.
+        auto read_ops = [&](int buf, int c, bool km, bf16x8 *va, bf16x8 *vb) {
             const u16 *si = sm.s_in[buf];
-            bf16x8 va[TM], vb[TN];
 #pragma unroll
             for (int i = 0; i < TM; ++i) {
                 const int rb = wave * 64 + 32 * i;
@@ -746,6 +765,8 @@ __device__ __forceinline__ void xres_run(const StageArgs &a1, const StageArgs *_
 #pragma unroll
             for (int j = 0; j < TN; ++j)
                 vb[j] = __builtin_bit_cast(bf16x8, *(const u16x8 *)&sm.s_x[(32 * j + r32) * kXresXS + c * KT + 8 * half]);
+        };
+        auto mma = [&](const bf16x8 *va, const bf16x8 *vb) {
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
                 if (j > 0 && n0 + 32 * j >= Nvalid) continue;   // no valid column in this subtile
@@ -759,20 +780,34 @@ __device__ __forceinline__ void xres_run(const StageArgs &a1, const StageArgs *_
             }
         };
 
-        // Loads go out PD chunks ahead, unconditionally (chunks past nbar
-        // read block 0 and store zeros); the loop runs a multiple of PD
-        // chunks so that each store waits for its own register stage only.
-        // Chunks past nbar skip their MFMAs (the X slice holds nothing past
-        // Kpad).
+        // Chunk c lives in register stage c mod PD and LDS buffer c mod 2.
+        // Iteration c reads chunk c's operands, stores chunk c + 1 into the
+        // other buffer and sends chunk c + 1 + PD's loads into the stage
+        // just freed, runs chunk c's MFMAs, then meets the barrier that
+        // publishes chunk c + 1 (and frees buffer c mod 2 for chunk c + 2).
+        // Loads and stores go out unconditionally (chunks past nbar read
+        // block 0 and store zeros; the last iteration's store lands in a
+        // buffer nothing reads before the epilogue's barrier), so that every
+        // wait is for the stage PD iterations old; chunks past nbar skip
+        // their MFMAs (the X slice holds nothing past Kpad).
+        static_assert(PD % 2 == 0, "the buffer of chunk c is fixed per unrolled step");
+        store_chunk(0, 0);
+        bool km_cur = rq0[0];
+        load_chunk(PD, 0);
+        __syncthreads();
         for (int c0 = 0; c0 < nch_pad; c0 += PD) {
 #pragma unroll
             for (int u = 0; u < PD; ++u) {
                 const int c = c0 + u;
-                store_chunk(c & 1, u);
-                const bool km = rq0[u];
+                const int un = (u + 1) % PD;
+                bf16x8 va[TM], vb[TN];
+                if (c < nbar) read_ops(u & 1, c, km_cur, va, vb);
+                const bool km_next = rq0[un];
+                store_chunk((u + 1) & 1, un);
+                load_chunk(c + 1 + PD, un);
+                if (c < nbar) mma(va, vb);
+                km_cur = km_next;
                 __syncthreads();
-                load_chunk(c + PD, u);
-                if (c < nbar) mfma_chunk(c & 1, c, km);
             }
         }
 
@@ -784,12 +819,12 @@ __device__ __forceinline__ void xres_run(const StageArgs &a1, const StageArgs *_
         auto opart = [&](int mm) { return (int64_t)(mm % B) * a.mos[0] + (int64_t)(mm / B) * a.mos[1] + fixed_off; };
         auto npart = [&](int ng) { return out_base + (int64_t)(ng / B) * out_jstride + (int64_t)(ng % B) * a.osk; };
         if constexpr (K == 0) {
-            float *out = (float *)a.out;
+            gfloat *out = (gfloat *)a.out;
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
                 const int ng = n0 + j * 32 + r32;
                 if (ng < Nvalid) {
-                    float *oj = out + npart(ng);
+                    gfloat *oj = out + npart(ng);
 #pragma unroll
                     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -802,7 +837,7 @@ __device__ __forceinline__ void xres_run(const StageArgs &a1, const StageArgs *_
         } else {
             __syncthreads();   // every wave is done with s_in, which s_out overlays
             u16 *so = sm.s_out[wave];
-            u16 *out = (u16 *)a.out;
+            gu16 *out = (gu16 *)a.out;
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -822,7 +857,7 @@ __device__ __forceinline__ void xres_run(const StageArgs &a1, const StageArgs *_
                         const u32x4 w = *(const u32x4 *)&so[col * kOutRow + run];
                         const int ng = n0 + j * 32 + col;
                         const int mm = wave * 64 + i * 32 + run;
-                        if (ng < Nvalid) *(u32x4 *)(out + npart(ng) + opart(mm)) = w;
+                        if (ng < Nvalid) *(gu32x4w *)(out + npart(ng) + opart(mm)) = w;
                     }
                     __builtin_amdgcn_wave_barrier();
                 }
