@@ -751,9 +751,18 @@ def main():
         rep_blocks = comb(pbar + m - 1, m) - comb(pbar, m)       # blocks with a repeated index
         nbytes = 2 * rep_blocks * bC ** m * 4
         gbs = nbytes / (ms_sym * 1e-3) / 1e9
+        # Yardstick: a plain device copy of the repeated-index blocks' bytes.
+        src = torch.empty(rep_blocks * bC ** m, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        ms_copy_sym = timed_op(lambda: dst.copy_(src))
+        copy_gbs = nbytes / (ms_copy_sym * 1e-3) / 1e9
+        del src, dst
         out["symmetrize"] = {"us": round(ms_sym * 1e3, 2), "algorithmic_mb": round(nbytes / 1e6, 2),
                              "achieved_gbs": round(gbs, 1), "peak_gbs": PEAK_HBM_GBS,
-                             "frac": round(gbs / PEAK_HBM_GBS, 4)}
+                             "frac": round(gbs / PEAK_HBM_GBS, 4),
+                             "plain_copy": {"us": round(ms_copy_sym * 1e3, 2), "mb": round(nbytes / 1e6, 2),
+                                            "gbs": round(copy_gbs, 1)},
+                             "frac_of_plain_copy_gbs": round(gbs / copy_gbs, 4)}
         del C2
 
     # The bf16 form on the same workload, reported beside the FP32 line.
