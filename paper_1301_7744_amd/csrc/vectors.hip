@@ -177,15 +177,41 @@ __global__ __launch_bounds__(256) void vec_block3_kernel(const E *__restrict__ A
     const VecEntry e0 = entries[blk_terms[t0]];
     const int64_t seg[3] = {(int64_t)e0.s[0] * B, (int64_t)e0.s[1] * B, (int64_t)e0.s[2] * B};
     const E *blk = A + r * (B * B * B);
-    for (int g = tid; g < B * B * B; g += 256) s_blk[(g % (B * B)) + (g / (B * B)) * S2] = ld(blk, g);
+    // (Loops with a fixed trip count, unrolled, so that each thread's loads
+    // all go out before the first one is waited for.)
+    constexpr int BLK_IT = (B * B * B + 255) / 256;
+#pragma unroll
+    for (int it = 0; it < BLK_IT; ++it) {
+        const int g = tid + 256 * it;
+        if (g < B * B * B) s_blk[(g % (B * B)) + (g / (B * B)) * S2] = ld(blk, g);
+    }
+    // The block's terms (one per distinct block index: at most 3), read once
+    // for every pass over the vectors.
+    const int nterm = t1 - t0;
+    int tidx[3] = {0, 0, 0}, tq[3] = {0, 0, 0};
+    float tw[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+        if (e < nterm) tidx[e] = blk_terms[t0 + e];
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+        if (e < nterm) {
+            tq[e] = entries[tidx[e]].q;
+            tw[e] = entries[tidx[e]].w;
+        }
     for (int64_t v0 = 0; v0 < V; v0 += VB) {
         const int64_t v = v0 + vl;
         const bool live = v < V;
         __syncthreads();   // the block is staged; the previous pass is done with s_x and s_red
-        for (int t = tid; t < 3 * VB * B; t += 256) {
-            const int j = t / (VB * B), vv = (t / B) % VB, d = t % B;
-            const int64_t xi = seg[j] + d, xv = v0 + vv;
-            s_x[j][vv][d] = (xv < V && xi < n) ? ld(x, xv * rs_x + xi) : 0.f;
+        constexpr int X_IT = (3 * VB * B + 255) / 256;
+#pragma unroll
+        for (int it = 0; it < X_IT; ++it) {
+            const int t = tid + 256 * it;
+            if (t < 3 * VB * B) {
+                const int j = t / (VB * B), vv = (t / B) % VB, d = t % B;
+                const int64_t xi = seg[j] + d, xv = v0 + vv;
+                s_x[j][vv][d] = (xv < V && xi < n) ? ld(x, xv * rs_x + xi) : 0.f;
+            }
         }
         __syncthreads();
         float x0[B], x1[B], T0[B], g1[B];
@@ -221,13 +247,20 @@ __global__ __launch_bounds__(256) void vec_block3_kernel(const E *__restrict__ A
             R0 += s_red[0][vl][k][d2];
             R1 += s_red[1][vl][k][d2];
         }
-        if (live)
-            for (int t = t0; t < t1; ++t) {
+        if (live) {
+#pragma unroll
+            for (int e = 0; e < 3; ++e)
+                if (e < nterm) {
+                    const float val = tq[e] == 0 ? R0 : (tq[e] == 1 ? R1 : T2);
+                    part[((int64_t)tidx[e] * V + v) * B + d2] = tw[e] * val;
+                }
+            for (int t = t0 + 3; t < t1; ++t) {   // more than 3 terms: never for m = 3
                 const int idx = blk_terms[t];
                 const int q = entries[idx].q;
                 const float val = q == 0 ? R0 : (q == 1 ? R1 : T2);
                 part[((int64_t)idx * V + v) * B + d2] = entries[idx].w * val;
             }
+        }
     }
 }
 
@@ -272,8 +305,21 @@ __global__ __launch_bounds__(256) void vec_rows_kernel(const float *__restrict__
     const int S = 256 / b;
     const int l = threadIdx.x % b, k = threadIdx.x / b;
     float acc = 0.f;
-    if (k < S)
-        for (int c = u_entry[u] + k; c < u_entry[u + 1]; c += S) acc += part[((int64_t)c * V + v) * b + l];
+    if (k < S) {
+        // entries c, c + S, ... in order, four loads out at a time
+        const int c1 = u_entry[u + 1];
+        for (int c = u_entry[u] + k; c < c1; c += 4 * S) {
+            float pv[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int cc = c + e * S;
+                pv[e] = cc < c1 ? part[((int64_t)cc * V + v) * b + l] : 0.f;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (c + e * S < c1) acc += pv[e];
+        }
+    }
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int h = S / 2; h > 0; h >>= 1) {
@@ -300,7 +346,14 @@ __global__ __launch_bounds__(256) void vec_dot_kernel(const float *__restrict__ 
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
     float t = 0.f;
-    for (int u = 0; u < nbar; ++u) t += dotp[(int64_t)u * V + v];
+    for (int u0 = 0; u0 < nbar; u0 += 8) {   // in block order, eight loads out at a time
+        float dv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dv[e] = u0 + e < nbar ? dotp[(int64_t)(u0 + e) * V + v] : 0.f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (u0 + e < nbar) t += dv[e];
+    }
     s[v] = t;
 }
 
