@@ -303,14 +303,45 @@ __global__ __launch_bounds__(256) void bcss_unpack_vec_kernel(const E *__restric
         const int64_t lim0 = n - tbj[0];
         __syncthreads();   // the previous block's reads of the staging buffer are done
         if (vec16 && sizeof(E) == 4) {
-            for (int v = threadIdx.x; v < bm / 4; v += blockDim.x) {
-                const uint4 w = ((const uint4 *)src)[v];
-                const int o = unpack_pad(4 * v);   // the four entries stay contiguous
-                uint32_t *d = (uint32_t *)sb + o;
-                d[0] = w.x;
-                d[1] = w.y;
-                d[2] = w.z;
-                d[3] = w.w;
+            // four vectors per thread in flight before the first is stored
+            constexpr int kU = 4;
+            for (int v0 = threadIdx.x; v0 < bm / 4; v0 += kU * blockDim.x) {
+                uint4 w[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int v = v0 + u * (int)blockDim.x;
+                    w[u] = v < bm / 4 ? ((const uint4 *)src)[v] : uint4{0u, 0u, 0u, 0u};
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int v = v0 + u * (int)blockDim.x;
+                    if (v >= bm / 4) continue;
+                    uint32_t *d = (uint32_t *)sb + unpack_pad(4 * v);   // the four entries stay contiguous
+                    d[0] = w[u].x;
+                    d[1] = w[u].y;
+                    d[2] = w[u].z;
+                    d[3] = w[u].w;
+                }
+            }
+        } else if (vec16 && sizeof(E) == 2) {
+            // eight entries per 16-byte vector, two vectors per thread in flight
+            constexpr int kU = 2;
+            for (int v0 = threadIdx.x; v0 < bm / 8; v0 += kU * blockDim.x) {
+                uint4 w[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int v = v0 + u * (int)blockDim.x;
+                    w[u] = v < bm / 8 ? ((const uint4 *)src)[v] : uint4{0u, 0u, 0u, 0u};
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int v = v0 + u * (int)blockDim.x;
+                    if (v >= bm / 8) continue;
+                    const uint32_t ww[4] = {w[u].x, w[u].y, w[u].z, w[u].w};
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        ((uint16_t *)sb)[unpack_pad(8 * v + e)] = (uint16_t)(ww[e >> 1] >> (16 * (e & 1)));
+                }
             }
         } else {
             for (int v = threadIdx.x; v < bm; v += blockDim.x) sb[unpack_pad(v)] = src[v];

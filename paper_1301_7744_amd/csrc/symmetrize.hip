@@ -131,12 +131,20 @@ __global__ __launch_bounds__(kSymThreads) void bcss_symmetrize_lds_kernel(
         }
         const int p0 = stab_start[mask], p1 = stab_start[mask + 1];
         const int np = p1 - p0;   // <= kSymMaxPerms (checked by the launcher)
+        // Every permutation's weights go to LDS with the block, so that the
+        // loops over the permutations below read them from LDS rather than
+        // waiting on a global read per permutation.
         if (lb < 0)
             for (int t = threadIdx.x; t < np * m; t += blockDim.x) {
                 const int pp = t / m, j = t - pp * m;   // position j holds mode perm[j]: weight b^j for that mode
                 int w = 1;
                 for (int e = 0; e < j; ++e) w *= b;
                 s_w[pp * kMaxOrder + stab_perm[(p0 + pp) * m + j]] = w;
+            }
+        else
+            for (int t = threadIdx.x; t < np * m; t += blockDim.x) {
+                const int pp = t / m, i = t - pp * m;   // mode i sits at position pinv(i): weight b^pinv(i)
+                s_w[pp * kMaxOrder + i] = 1 << (stab_pinv[(int64_t)(p0 + pp) * kMaxOrder + i] * lb);
             }
         __syncthreads();
         auto digits = [&](int l, int *d) {
@@ -159,14 +167,8 @@ __global__ __launch_bounds__(kSymThreads) void bcss_symmetrize_lds_kernel(
         };
         // Weights of permutation pp (uniform over the workgroup): b^pinv(i).
         auto weights = [&](int pp, int *w) {
-            if (lb >= 0) {
-                const int32_t *pv = stab_pinv + (int64_t)(p0 + pp) * kMaxOrder;
 #pragma unroll
-                for (int i = 0; i < kMaxOrder; ++i) w[i] = i < m ? 1 << (pv[i] * lb) : 0;
-            } else {
-#pragma unroll
-                for (int i = 0; i < kMaxOrder; ++i) w[i] = i < m ? s_w[pp * kMaxOrder + i] : 0;
-            }
+            for (int i = 0; i < kMaxOrder; ++i) w[i] = i < m ? s_w[pp * kMaxOrder + i] : 0;
         };
         auto image = [&](const int *d, const int *w) {
             int o = 0;
